@@ -1,0 +1,91 @@
+"""Planted mistakes in the oracle must each fail at least one pin.
+
+Each case patches one plausible error into the oracle (on the CPU only) and
+runs the pins that should catch it.
+"""
+import numpy as np
+import pytest
+
+from oracle import adct_oracle as O
+import tests.test_oracle_pins as P
+
+
+def _fails(fn, *args):
+    try:
+        fn(*args)
+    except (AssertionError, ValueError):
+        return True
+    return False
+
+
+@pytest.fixture
+def orig_T():
+    return O.transform_matrix()
+
+
+def test_wrong_sign_in_T_is_caught(monkeypatch, orig_T, golden_dir):
+    bad = orig_T.copy()
+    bad[6, 5] = -bad[6, 5]
+    monkeypatch.setattr(O, "transform_matrix", lambda: bad.copy())
+    assert _fails(P.test_factorisation_equals_T) or _fails(P.test_scaling_matches_printed_S, golden_dir)
+    assert _fails(P.test_fast_algorithm_basis_vectors)
+
+
+def test_swapped_rows_of_T_are_caught(monkeypatch, orig_T, golden_dir):
+    bad = orig_T[[0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 14, 13, 15]].copy()
+    monkeypatch.setattr(O, "transform_matrix", lambda: bad.copy())
+    assert _fails(P.test_factorisation_equals_T)
+    assert _fails(P.test_table2_rows, golden_dir) or _fails(P.test_scaling_matches_printed_S, golden_dir)
+
+
+def test_transposed_operand_in_fwd2d_is_caught(monkeypatch):
+    def bad_fwd2d(img):
+        T = O.transform_matrix()
+        A = O.to_tiles(np.asarray(img).astype(np.int64))
+        return np.einsum("ui,kji,vj->kuv", T, A, T)  # A transposed
+    monkeypatch.setattr(O, "fwd2d", bad_fwd2d)
+    assert _fails(P.test_fwd2d_basis_tiles_brute_force)
+
+
+def test_wrong_zonal_weight_is_caught(monkeypatch):
+    W = O.zonal_weights()
+    bad = W.copy()
+    bad[3, 3] *= 2
+    monkeypatch.setattr(O, "zonal_weights", lambda: bad.copy())
+    assert _fails(P.test_zonal_full_keep_is_lossless)
+    assert _fails(P.test_identity_weighted_roundtrip_is_256X)
+
+
+def test_round_half_even_is_caught(monkeypatch):
+    monkeypatch.setattr(O, "round_half_away", lambda v: np.rint(np.asarray(v, np.float64)).astype(np.int64))
+    assert _fails(P.test_quant_small_values_are_zero)
+
+
+def test_dropped_rounding_offset_is_caught(monkeypatch):
+    monkeypatch.setattr(O, "round_clamp", lambda R, lo, hi: np.clip(np.floor_divide(R, 256), lo, hi))
+    assert _fails(P.test_zonal_r1_is_rounded_block_mean)
+
+
+def test_wrong_quant_step_is_caught(monkeypatch):
+    monkeypatch.setattr(O, "quant_step", lambda qp: float(np.exp2((qp - 4) / 5.0)))
+    assert _fails(P.test_quant_step_closed_form)
+
+
+def test_psnr_missing_pixel_count_is_caught(monkeypatch):
+    import math
+    monkeypatch.setattr(O, "psnr", lambda s, n, peak=255.0: math.inf if s == 0 else 10 * math.log10(peak * peak / s))
+    assert _fails(P.test_psnr_closed_forms)
+
+
+def test_wrong_stage_block_is_caught(monkeypatch):
+    good = O.stage_M4()
+    bad = good.copy()
+    bad[1, 1] = 1  # [[1,1],[1,-1]] -> [[1,1],[1,1]]
+    monkeypatch.setattr(O, "stage_M4", lambda: bad.copy())
+    assert _fails(P.test_factorisation_equals_T)
+    assert _fails(P.test_fast_algorithm_basis_vectors)
+
+
+def test_dropped_permutation_is_caught(monkeypatch):
+    monkeypatch.setattr(O, "P1_CYCLES", ())
+    assert _fails(P.test_factorisation_equals_T)
