@@ -1,0 +1,180 @@
+/*
+ * adct.h -- C ABI of the MI355X (gfx950) blockwise 16-point multiplierless
+ * approximate DCT library (libadct.so).
+ *
+ * The method: Silveira et al., "Multiplierless 16-point DCT approximation
+ * for low-complexity image and video coding".  A 16x16 matrix T over
+ * {0, +1, -1} (Section 2.1) is applied to every disjoint 16x16 block A of a
+ * plane as Y = T A T^T (Section 3.1), each 1D pass with the 44-addition
+ * factorisation T = P2 M4 M3 M2 P1 M1 (Section 2.2).  The orthogonalising
+ * diagonal S = sqrt((T T^T)^-1) (Section 2.1) is never applied as a separate
+ * step: it is folded into the quantisation / dequantisation scale factors
+ * or into the zonal weights (Section 2.1, last paragraph).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Return value: ADCT_OK (0) or a negative ADCT_E_* code; adct_strerror()
+ *   names it.  Arguments are validated before anything is launched; a call
+ *   that returns an error has launched nothing.
+ * - "Device" pointers are HIP device (or managed) memory owned by the
+ *   caller.  Plain calls never allocate, never synchronise, and are
+ *   asynchronous on `stream` (a hipStream_t passed as void*; NULL = the
+ *   legacy default stream).  Faults inside a kernel surface at the caller's
+ *   next synchronisation of that stream.
+ * - Plain calls keep no state and may be issued from several host threads.
+ * - Planes (adct_plane) are row-major with a byte pitch; height and width
+ *   are positive multiples of 16 (else ADCT_E_SHAPE); the pitch is at least
+ *   width * sample size and a multiple of the sample size.  Sample (0,0)
+ *   must be 16-byte aligned and the pitch a multiple of 16 bytes.
+ * - Coefficient-domain arrays are block-major: [nblk][16][16], block
+ *   k = by * (width/16) + bx in raster order, element u*16 + v, u the
+ *   vertical and v the horizontal frequency.  They must be 16-byte aligned.
+ * - A batch of equally sized images is passed as one tall plane (images
+ *   stacked vertically); `image_height` then names each image's height so
+ *   that per-image sums of squared errors can be formed.
+ */
+#ifndef ADCT_H
+#define ADCT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ADCT_ABI_VERSION 1
+
+/* ---- status codes ---------------------------------------------------- */
+#define ADCT_OK            0
+#define ADCT_PENDING       1   /* adct_server_poll: request not finished yet  */
+#define ADCT_E_ARG        -1   /* null / out-of-range argument                */
+#define ADCT_E_SHAPE      -2   /* side not a positive multiple of 16, pitch   */
+#define ADCT_E_DTYPE      -3   /* sample type not supported by this call      */
+#define ADCT_E_HIP        -4   /* a HIP runtime call failed                   */
+#define ADCT_E_NOMEM      -5   /* library-owned allocation failed             */
+#define ADCT_E_TOO_LARGE  -6   /* request can never fit the server's pool     */
+#define ADCT_E_STOPPED    -7   /* server stopped; request cancelled           */
+#define ADCT_E_TIMEOUT    -8   /* bounded wait expired                        */
+#define ADCT_E_NOTFOUND   -9   /* unknown ticket / tuning entry               */
+#define ADCT_E_ALIGN     -10   /* pointer or pitch misaligned                 */
+
+/* ---- sample types ---------------------------------------------------- */
+#define ADCT_U8   1   /* uint8 image samples, reconstruction clamped to [0,255]    */
+#define ADCT_I16  2   /* int16 residual samples, reconstruction clamped to [-255,255] */
+
+typedef struct adct_plane {
+    void*   data;        /* device pointer to sample (0,0)                 */
+    int32_t dtype;       /* ADCT_U8 or ADCT_I16                            */
+    int32_t height;      /* rows, positive multiple of 16                  */
+    int32_t width;       /* samples per row, positive multiple of 16       */
+    int32_t reserved;
+    int64_t pitch_bytes; /* bytes from one row to the next                 */
+} adct_plane;
+
+/* ---- host-side information ---------------------------------------------- */
+
+/* Message for a status code (static string, never NULL). */
+const char* adct_strerror(int code);
+
+/* ADCT_ABI_VERSION of the loaded library. */
+int adct_abi_version(void);
+
+/* Host copies of the library's constants (Section 2.1): T (row-major,
+ * T[u*16+j]), the diagonal s of S = sqrt((T T^T)^-1), and the zonal weights
+ * W[u*16+v] = 256 / (d_u d_v), d = diag(T T^T).  Any pointer may be NULL. */
+int adct_constants(int32_t* T256, double* s16, int32_t* W256);
+
+/* Host copies of the quantisation tables for `qp` (Section 2.1: S merged
+ * into the quantiser).  Step Delta = 2^((qp-4)/6), qp in [0, 63].
+ *   qs[u*16+v]  = fp32(s_u s_v / Delta)        (forward scale)
+ *   dqs[u*16+v] = fp32(256 Delta s_u s_v)      (dequantise to 8 fractional bits)
+ * Both are computed in double and rounded once to float.  Either pointer may
+ * be NULL.  ADCT_E_ARG for qp outside [0, 63]. */
+int adct_quant_tables(int qp, float* qs256, float* dqs256);
+
+/* PSNR per image from exact sums of squared errors (host arrays):
+ * out[i] = 10 log10(peak^2 * pixels_per_image / sse[i]), +inf when sse is 0. */
+int adct_psnr(const int64_t* sse, int32_t n, double pixels_per_image, double peak,
+              double* out);
+
+/* The kernels' own 1D butterflies executed on the host (the same source the
+ * GPU runs): X = T x (inverse = 0) or x = T^T X (inverse = 1), Section 2.2's
+ * 44-addition dataflow.  For checking the dataflow without a GPU.
+ * in16, out16: host int32[16]. */
+int adct_host_butterfly(int32_t inverse, const int32_t* in16, int32_t* out16);
+
+/* ---- plain device calls -------------------------------------------------- */
+
+/* Forward transform Y = T A T^T of every 16x16 block of `src` (Section 3.1;
+ * each 1D pass by the Section 2.2 factorisation, 44 additions).
+ * src: U8 or I16 plane.  coef: device int32 [nblk][16][16].
+ * Exact (bit-identical to the integer matrix product): |Y| <= 65280 for U8
+ * samples and for I16 samples within [-255, 255]; any I16 input is exact. */
+int adct_fwd2d(const adct_plane* src, int32_t* coef, void* stream);
+
+/* Plain inverse R = T^T Y T of `nblk` blocks (Section 3.1, without S).
+ * coef, out: device int32 [nblk][16][16].  Exact while every |R| < 2^31
+ * (guaranteed for |Y| < 2^25); otherwise wraps modulo 2^32.  Because
+ * T^T T is not diagonal this is not the inverse of adct_fwd2d; see
+ * adct_zonal / adct_dequant for the S-weighted inverse path. */
+int adct_inv2d(const int32_t* coef, int64_t nblk, int32_t* out, void* stream);
+
+/* Orthonormal coefficients B = S Y S (Section 2.1, C-hat = S T):
+ * out[k][u][v] = fp32(Y) * fp32(s_u s_v), one rounding each.
+ * coef: device int32, out: device float32, both [nblk][16][16]. */
+int adct_scale(const int32_t* coef, int64_t nblk, float* out, void* stream);
+
+/* Quantisation levels with S folded in (Section 2.1; uniform step
+ * Delta = 2^((qp-4)/6), round half away from zero, no dead zone):
+ * q = round(fp32(Y) * qs[u][v]) saturated to int16.  coef: device int32,
+ * q: device int16, [nblk][16][16]. */
+int adct_quant(const int32_t* coef, int64_t nblk, int qp, int16_t* q, void* stream);
+
+/* Dequantisation to 8 fractional bits with S folded in:
+ * zfix = round(fp32(q) * dqs[u][v]) (half away from zero), int32.
+ * q: device int16, zfix: device int32, [nblk][16][16]. */
+int adct_dequant(const int16_t* q, int64_t nblk, int qp, int32_t* zfix, void* stream);
+
+/* Zonal retention of the top-left r x r coefficients (Section 3.1), S folded
+ * in as zfix = Y * W[u][v] for u < r and v < r, 0 elsewhere
+ * (W = 256/(d_u d_v), a left shift by 0..4).  r in [0, 16].
+ * coef, zfix: device int32 [nblk][16][16]. */
+int adct_zonal(const int32_t* coef, int64_t nblk, int r, int32_t* zfix, void* stream);
+
+/* Reconstruction from 8-fractional-bit coefficients (Section 3.1 inverse):
+ * R = T^T zfix T per block, sample = clamp(floor((R + 128) / 256)) to
+ * [0, 255] (U8) or [-255, 255] (I16), written into the plane `dst`, whose
+ * shape fixes nblk.  zfix: device int32 [nblk][16][16]; exact while
+ * |R| < 2^31. */
+int adct_recon(const int32_t* zfix, const adct_plane* dst, void* stream);
+
+/* Exact per-image sums of squared differences between two planes of the same
+ * shape and type; images are the consecutive bands of `image_height` rows
+ * (a positive multiple of 16 dividing the plane height).
+ * sse: device int64 [height / image_height], overwritten. */
+int adct_sse(const adct_plane* a, const adct_plane* b, int32_t image_height,
+             int64_t* sse, void* stream);
+
+/* ---- fused device calls (one pass over HBM each) --------------------- */
+
+/* adct_fwd2d followed by adct_quant, without storing Y. */
+int adct_fwd2d_quant(const adct_plane* src, int qp, int16_t* q, void* stream);
+
+/* adct_zonal followed by adct_recon, and -- when `ref` and `sse` are both
+ * non-NULL -- adct_sse of the reconstruction against `ref` (same shape and
+ * type as dst) with images of `image_height` rows.  Only the kept r x r
+ * coefficients of each block are read.  dst may alias nothing else. */
+int adct_zonal_recon(const int32_t* coef, int r, const adct_plane* dst,
+                     const adct_plane* ref, int32_t image_height, int64_t* sse,
+                     void* stream);
+
+/* adct_dequant followed by adct_recon (and the optional SSE, as above). */
+int adct_dequant_recon(const int16_t* q, int qp, const adct_plane* dst,
+                       const adct_plane* ref, int32_t image_height, int64_t* sse,
+                       void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ADCT_H */

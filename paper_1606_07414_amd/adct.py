@@ -1,0 +1,274 @@
+"""Python binding of libadct.so: argument marshalling only.
+
+Every function has the name of the C entry point it calls (without the
+``adct_`` prefix).  Torch tensors provide device memory and the stream; all
+arithmetic runs in the library's HIP kernels.  If the library is missing
+this module raises on import of the first call -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libadct.so")
+
+OK, PENDING = 0, 1
+E_ARG, E_SHAPE, E_DTYPE, E_HIP, E_NOMEM, E_TOO_LARGE, E_STOPPED, E_TIMEOUT, E_NOTFOUND, E_ALIGN = (
+    -1, -2, -3, -4, -5, -6, -7, -8, -9, -10)
+U8, I16 = 1, 2
+
+
+class AdctError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {_lib().adct_strerror(code).decode()} ({code})")
+
+
+class Plane(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("dtype", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("width", ctypes.c_int32), ("reserved", ctypes.c_int32), ("pitch_bytes", ctypes.c_int64)]
+
+
+_P = ctypes.c_void_p
+_PP = ctypes.POINTER(Plane)
+_I32, _I64, _D = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+
+_SIGNATURES = {
+    "adct_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "adct_abi_version": (ctypes.c_int, []),
+    "adct_constants": (ctypes.c_int, [_P, _P, _P]),
+    "adct_quant_tables": (ctypes.c_int, [ctypes.c_int, _P, _P]),
+    "adct_psnr": (ctypes.c_int, [_P, _I32, _D, _D, _P]),
+    "adct_host_butterfly": (ctypes.c_int, [_I32, _P, _P]),
+    "adct_fwd2d": (ctypes.c_int, [_PP, _P, _P]),
+    "adct_inv2d": (ctypes.c_int, [_P, _I64, _P, _P]),
+    "adct_scale": (ctypes.c_int, [_P, _I64, _P, _P]),
+    "adct_quant": (ctypes.c_int, [_P, _I64, ctypes.c_int, _P, _P]),
+    "adct_dequant": (ctypes.c_int, [_P, _I64, ctypes.c_int, _P, _P]),
+    "adct_zonal": (ctypes.c_int, [_P, _I64, ctypes.c_int, _P, _P]),
+    "adct_recon": (ctypes.c_int, [_P, _PP, _P]),
+    "adct_sse": (ctypes.c_int, [_PP, _PP, _I32, _P, _P]),
+    "adct_fwd2d_quant": (ctypes.c_int, [_PP, ctypes.c_int, _P, _P]),
+    "adct_zonal_recon": (ctypes.c_int, [_P, ctypes.c_int, _PP, _PP, _I32, _P, _P]),
+    "adct_dequant_recon": (ctypes.c_int, [_P, ctypes.c_int, _PP, _PP, _I32, _P, _P]),
+}
+
+_LIB = None
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"libadct.so not built at {LIB_PATH}: run __graft_entry__.build()")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = lib
+    return _LIB
+
+
+def lib():
+    """The loaded ctypes library (loads it on first use)."""
+    return _lib()
+
+
+def _check(rc: int, where: str) -> int:
+    if rc < 0:
+        raise AdctError(rc, where)
+    return rc
+
+
+# ---------------------------------------------------------------- marshalling
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream):
+    if stream is None:
+        return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
+    return ctypes.c_void_p(getattr(stream, "cuda_stream", stream))
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.uint8:
+        return U8
+    if t.dtype == torch.int16:
+        return I16
+    raise AdctError(E_DTYPE, "plane")
+
+
+def plane(t) -> Plane:
+    """Descriptor of a 2D device tensor (rows may be padded: stride(0) is the pitch)."""
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise AdctError(E_SHAPE, "plane")
+    return Plane(t.data_ptr(), _dtype_code(t), t.shape[0], t.shape[1], 0, t.stride(0) * t.element_size())
+
+
+def _blocks(t, dtype, where):
+    torch = _torch()
+    if t.dtype != dtype or not t.is_contiguous() or t.numel() % 256:
+        raise AdctError(E_ARG, where)
+    return t.numel() // 256
+
+
+def _new_blocks(n, dtype, like):
+    return _torch().empty((n, 16, 16), dtype=dtype, device=like.device)
+
+
+def _nblk_plane(t):
+    return (t.shape[0] // 16) * (t.shape[1] // 16)
+
+
+# ---------------------------------------------------------------- host calls
+def strerror(code: int) -> str:
+    return _lib().adct_strerror(code).decode()
+
+
+def abi_version() -> int:
+    return _lib().adct_abi_version()
+
+
+def constants():
+    T = np.empty(256, np.int32)
+    s = np.empty(16, np.float64)
+    W = np.empty(256, np.int32)
+    _check(_lib().adct_constants(T.ctypes.data, s.ctypes.data, W.ctypes.data), "constants")
+    return T.reshape(16, 16), s, W.reshape(16, 16)
+
+
+def quant_tables(qp: int):
+    qs = np.empty(256, np.float32)
+    dqs = np.empty(256, np.float32)
+    _check(_lib().adct_quant_tables(qp, qs.ctypes.data, dqs.ctypes.data), "quant_tables")
+    return qs.reshape(16, 16), dqs.reshape(16, 16)
+
+
+def psnr(sse, pixels_per_image: float, peak: float = 255.0) -> np.ndarray:
+    sse = np.ascontiguousarray(np.asarray(sse, dtype=np.int64).reshape(-1))
+    out = np.empty(sse.shape[0], np.float64)
+    _check(_lib().adct_psnr(sse.ctypes.data, sse.shape[0], pixels_per_image, peak, out.ctypes.data), "psnr")
+    return out
+
+
+def host_butterfly(x, inverse: bool = False) -> np.ndarray:
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.int32).reshape(16))
+    y = np.empty(16, np.int32)
+    _check(_lib().adct_host_butterfly(1 if inverse else 0, x.ctypes.data, y.ctypes.data), "host_butterfly")
+    return y
+
+
+# ---------------------------------------------------------------- device calls
+def fwd2d(src, coef=None, stream=None):
+    torch = _torch()
+    if coef is None:
+        coef = _new_blocks(_nblk_plane(src), torch.int32, src)
+    p = plane(src)
+    _check(_lib().adct_fwd2d(ctypes.byref(p), coef.data_ptr(), _stream(stream)), "fwd2d")
+    return coef
+
+
+def fwd2d_quant(src, qp: int, q=None, stream=None):
+    torch = _torch()
+    if q is None:
+        q = _new_blocks(_nblk_plane(src), torch.int16, src)
+    p = plane(src)
+    _check(_lib().adct_fwd2d_quant(ctypes.byref(p), qp, q.data_ptr(), _stream(stream)), "fwd2d_quant")
+    return q
+
+
+def inv2d(coef, out=None, stream=None):
+    torch = _torch()
+    n = _blocks(coef, torch.int32, "inv2d")
+    if out is None:
+        out = _new_blocks(n, torch.int32, coef)
+    _check(_lib().adct_inv2d(coef.data_ptr(), n, out.data_ptr(), _stream(stream)), "inv2d")
+    return out
+
+
+def scale(coef, out=None, stream=None):
+    torch = _torch()
+    n = _blocks(coef, torch.int32, "scale")
+    if out is None:
+        out = _new_blocks(n, torch.float32, coef)
+    _check(_lib().adct_scale(coef.data_ptr(), n, out.data_ptr(), _stream(stream)), "scale")
+    return out
+
+
+def quant(coef, qp: int, q=None, stream=None):
+    torch = _torch()
+    n = _blocks(coef, torch.int32, "quant")
+    if q is None:
+        q = _new_blocks(n, torch.int16, coef)
+    _check(_lib().adct_quant(coef.data_ptr(), n, qp, q.data_ptr(), _stream(stream)), "quant")
+    return q
+
+
+def dequant(q, qp: int, zfix=None, stream=None):
+    torch = _torch()
+    n = _blocks(q, torch.int16, "dequant")
+    if zfix is None:
+        zfix = _new_blocks(n, torch.int32, q)
+    _check(_lib().adct_dequant(q.data_ptr(), n, qp, zfix.data_ptr(), _stream(stream)), "dequant")
+    return zfix
+
+
+def zonal(coef, r: int, zfix=None, stream=None):
+    torch = _torch()
+    n = _blocks(coef, torch.int32, "zonal")
+    if zfix is None:
+        zfix = _new_blocks(n, torch.int32, coef)
+    _check(_lib().adct_zonal(coef.data_ptr(), n, r, zfix.data_ptr(), _stream(stream)), "zonal")
+    return zfix
+
+
+def recon(zfix, dst, stream=None):
+    p = plane(dst)
+    _check(_lib().adct_recon(zfix.data_ptr(), ctypes.byref(p), _stream(stream)), "recon")
+    return dst
+
+
+def _ref_args(ref, image_height, sse, dst):
+    torch = _torch()
+    if ref is None:
+        return None, 0, None, None
+    if image_height is None:
+        image_height = dst.shape[0]
+    if sse is None:
+        sse = torch.empty(dst.shape[0] // image_height, dtype=torch.int64, device=dst.device)
+    return plane(ref), image_height, sse, sse.data_ptr()
+
+
+def zonal_recon(coef, r: int, dst, ref=None, image_height=None, sse=None, stream=None):
+    p = plane(dst)
+    rp, ih, sse, sp = _ref_args(ref, image_height, sse, dst)
+    _check(_lib().adct_zonal_recon(coef.data_ptr(), r, ctypes.byref(p), ctypes.byref(rp) if rp else None,
+                                   ih, sp, _stream(stream)), "zonal_recon")
+    return sse
+
+
+def dequant_recon(q, qp: int, dst, ref=None, image_height=None, sse=None, stream=None):
+    p = plane(dst)
+    rp, ih, sse, sp = _ref_args(ref, image_height, sse, dst)
+    _check(_lib().adct_dequant_recon(q.data_ptr(), qp, ctypes.byref(p), ctypes.byref(rp) if rp else None,
+                                     ih, sp, _stream(stream)), "dequant_recon")
+    return sse
+
+
+def sse(a, b, image_height=None, out=None, stream=None):
+    torch = _torch()
+    if image_height is None:
+        image_height = a.shape[0]
+    if out is None:
+        out = torch.empty(a.shape[0] // image_height, dtype=torch.int64, device=a.device)
+    pa, pb = plane(a), plane(b)
+    _check(_lib().adct_sse(ctypes.byref(pa), ctypes.byref(pb), image_height, out.data_ptr(), _stream(stream)),
+           "sse")
+    return out

@@ -1,0 +1,101 @@
+// 16-point multiplierless approximate DCT: the 1D butterflies.
+//
+// T (Section 2.1) is applied through its sparse factorisation
+// T = P2 M4 M3 M2 P1 M1 (Section 2.2).  The stages are folded by hand into
+// one straight-line dataflow: M1 is the outer butterfly (16 add/sub), M2 the
+// two 8-point butterflies (16), M3 the two 4-point butterflies (8; its -I4
+// blocks are absorbed into operand order), M4 the final 2-point butterflies
+// (4; its sign-only rows absorbed likewise), and P1/P2 are only the naming
+// of outputs.  The result is exactly 44 additions/subtractions, no
+// negations, multiplies or shifts.  Outputs become final at different depths:
+// eight after two stages, four after three, four after four.
+//
+// The inverse direction applies T^T = M1 P1^T M2 M3 M4 P2^T (all M_i are
+// symmetric): the same graph mirrored, again 44 additions/subtractions.
+//
+// V may be any type with exact + and - over the values it carries
+// (int32, or a packed pair of int16 lanes, or float on integers < 2^24).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace adct {
+
+// log2 of d_k = (T T^T)_kk = (16,16,4,8,8,16,4,4,16,4,4,8,8,4,4,4), packed
+// two bits per k as (log2 d_k - 2).
+constexpr uint32_t kLog2NormPacked =
+    (2u << 0) | (2u << 2) | (0u << 4) | (1u << 6) | (1u << 8) | (2u << 10) | (0u << 12) |
+    (0u << 14) | (2u << 16) | (0u << 18) | (0u << 20) | (1u << 22) | (1u << 24) | (0u << 26) |
+    (0u << 28) | (0u << 30);
+
+__host__ __device__ constexpr int log2_norm(int k) {
+    return (int)((kLog2NormPacked >> (2 * k)) & 3u) + 2;
+}
+
+// X = T x.
+template <typename V>
+__host__ __device__ __forceinline__ void fwd16(const V (&x)[16], V (&X)[16]) {
+    // M1: outer butterfly
+    const V a0 = x[0] + x[15], a1 = x[1] + x[14], a2 = x[2] + x[13], a3 = x[3] + x[12];
+    const V a4 = x[4] + x[11], a5 = x[5] + x[10], a6 = x[6] + x[9], a7 = x[7] + x[8];
+    const V a8 = x[7] - x[8], a9 = x[6] - x[9], a10 = x[5] - x[10], a11 = x[4] - x[11];
+    const V a12 = x[3] - x[12], a13 = x[2] - x[13], a14 = x[1] - x[14], a15 = x[0] - x[15];
+    // M2 (after P1): the even half and the odd half, 8-point butterflies;
+    // the difference outputs are final coefficients.
+    const V b0 = a0 + a7, b1 = a1 + a6, b2 = a2 + a5, b3 = a3 + a4;
+    X[2] = a0 - a7;
+    X[10] = a6 - a1;
+    X[6] = a5 - a2;
+    X[14] = a4 - a3;
+    const V b8 = a8 + a9, b9 = a11 + a10, b10 = a12 + a13, b11 = a15 + a14;
+    X[7] = a8 - a9;
+    X[15] = a10 - a11;
+    X[9] = a12 - a13;
+    X[13] = a15 - a14;
+    // M3: 4-point butterflies
+    const V c0 = b0 + b3, c1 = b1 + b2, c8 = b8 + b11, c9 = b9 + b10;
+    X[4] = b0 - b3;
+    X[12] = b2 - b1;
+    X[3] = b11 - b8;
+    X[11] = b10 - b9;
+    // M4: 2-point butterflies
+    X[0] = c0 + c1;
+    X[8] = c0 - c1;
+    X[1] = c8 + c9;
+    X[5] = c8 - c9;
+}
+
+// x = T^T X.
+template <typename V>
+__host__ __device__ __forceinline__ void inv16(const V (&X)[16], V (&x)[16]) {
+    // M4 (after P2^T)
+    const V c0 = X[0] + X[8], c1 = X[0] - X[8], c8 = X[1] + X[5], c9 = X[1] - X[5];
+    // M3
+    const V b0 = c0 + X[4], b3 = c0 - X[4], b1 = c1 - X[12], b2 = c1 + X[12];
+    const V b8 = c8 - X[3], b11 = c8 + X[3], b9 = c9 - X[11], b10 = c9 + X[11];
+    // M2
+    const V p0 = b0 + X[2], p7 = b0 - X[2], p1 = b1 - X[10], p6 = b1 + X[10];
+    const V p2 = b2 - X[6], p5 = b2 + X[6], p3 = b3 - X[14], p4 = b3 + X[14];
+    const V p8 = b8 + X[7], p15 = b8 - X[7], p9 = b9 - X[15], p14 = b9 + X[15];
+    const V p10 = b10 + X[9], p13 = b10 - X[9], p11 = b11 + X[13], p12 = b11 - X[13];
+    // P1^T, then M1
+    x[0] = p0 + p11;
+    x[15] = p0 - p11;
+    x[1] = p1 + p12;
+    x[14] = p1 - p12;
+    x[2] = p2 + p13;
+    x[13] = p2 - p13;
+    x[3] = p3 + p10;
+    x[12] = p3 - p10;
+    x[4] = p4 + p9;
+    x[11] = p4 - p9;
+    x[5] = p5 + p14;
+    x[10] = p5 - p14;
+    x[6] = p6 + p15;
+    x[9] = p6 - p15;
+    x[7] = p7 + p8;
+    x[8] = p7 - p8;
+}
+
+}  // namespace adct

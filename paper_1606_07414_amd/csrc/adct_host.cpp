@@ -1,0 +1,135 @@
+// Host-only parts of the C ABI: status strings, constants, quantisation
+// tables and PSNR.  No HIP calls, so all of it runs without a GPU.
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include "adct.h"
+#include "adct_internal.hpp"
+
+namespace adct {
+
+// T of Section 2.1 (library copy; row u is output frequency u).
+static const int8_t kT[16][16] = {
+    {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1},
+    {1, 1, 1, 1, 1, 1, 1, 1, -1, -1, -1, -1, -1, -1, -1, -1},
+    {1, 0, 0, 0, 0, 0, 0, -1, -1, 0, 0, 0, 0, 0, 0, 1},
+    {1, 1, 0, 0, 0, 0, -1, -1, 1, 1, 0, 0, 0, 0, -1, -1},
+    {1, 0, 0, -1, -1, 0, 0, 1, 1, 0, 0, -1, -1, 0, 0, 1},
+    {1, 1, -1, -1, -1, -1, 1, 1, -1, -1, 1, 1, 1, 1, -1, -1},
+    {0, 0, -1, 0, 0, 1, 0, 0, 0, 0, 1, 0, 0, -1, 0, 0},
+    {0, 0, 0, 0, 0, 0, -1, 1, -1, 1, 0, 0, 0, 0, 0, 0},
+    {1, -1, -1, 1, 1, -1, -1, 1, 1, -1, -1, 1, 1, -1, -1, 1},
+    {0, 0, -1, 1, 0, 0, 0, 0, 0, 0, 0, 0, -1, 1, 0, 0},
+    {0, -1, 0, 0, 0, 0, 1, 0, 0, 1, 0, 0, 0, 0, -1, 0},
+    {0, 0, 1, 1, -1, -1, 0, 0, 0, 0, 1, 1, -1, -1, 0, 0},
+    {0, -1, 1, 0, 0, 1, -1, 0, 0, -1, 1, 0, 0, 1, -1, 0},
+    {1, -1, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, -1},
+    {0, 0, 0, -1, 1, 0, 0, 0, 0, 0, 0, 1, -1, 0, 0, 0},
+    {0, 0, 0, 0, -1, 1, 0, 0, 0, 0, -1, 1, 0, 0, 0, 0},
+};
+
+static int row_norm(int u) {
+    int d = 0;
+    for (int j = 0; j < 16; ++j) d += kT[u][j] * kT[u][j];
+    return d;
+}
+
+// s_u s_v for a class c = log2 d_u + log2 d_v - 4: 1 / sqrt(d_u d_v).
+static double class_ss(int c) { return 1.0 / sqrt((double)(1 << (c + 4))); }
+
+bool quant_scales(int qp, Scale5Host* qs, Scale5Host* dqs) {
+    if (qp < 0 || qp > 63) return false;
+    const double delta = exp2((qp - 4) / 6.0);
+    for (int c = 0; c < 5; ++c) {
+        const double ss = class_ss(c);
+        if (qs) qs->f[c] = (float)(ss / delta);
+        if (dqs) dqs->f[c] = (float)(256.0 * delta * ss);
+    }
+    return true;
+}
+
+void ortho_scales(Scale5Host* ss) {
+    for (int c = 0; c < 5; ++c) ss->f[c] = (float)class_ss(c);
+}
+
+int class_of(int u, int v) {
+    int lu = 0, lv = 0;
+    for (int d = row_norm(u); d > 1; d >>= 1) ++lu;
+    for (int d = row_norm(v); d > 1; d >>= 1) ++lv;
+    return lu + lv - 4;
+}
+
+}  // namespace adct
+
+using namespace adct;
+
+extern "C" {
+
+const char* adct_strerror(int code) {
+    switch (code) {
+        case ADCT_OK: return "ok";
+        case ADCT_PENDING: return "pending";
+        case ADCT_E_ARG: return "invalid argument";
+        case ADCT_E_SHAPE: return "plane sides must be positive multiples of 16 with a valid pitch";
+        case ADCT_E_DTYPE: return "unsupported sample type";
+        case ADCT_E_HIP: return "HIP runtime error";
+        case ADCT_E_NOMEM: return "out of memory";
+        case ADCT_E_TOO_LARGE: return "request larger than the memory pool";
+        case ADCT_E_STOPPED: return "stopped";
+        case ADCT_E_TIMEOUT: return "timed out";
+        case ADCT_E_NOTFOUND: return "not found";
+        case ADCT_E_ALIGN: return "pointer or pitch not 16-byte aligned";
+        default: return "unknown status";
+    }
+}
+
+int adct_abi_version(void) { return ADCT_ABI_VERSION; }
+
+int adct_constants(int32_t* T256, double* s16, int32_t* W256) {
+    for (int u = 0; u < 16; ++u) {
+        if (T256)
+            for (int j = 0; j < 16; ++j) T256[u * 16 + j] = kT[u][j];
+        if (s16) s16[u] = 1.0 / sqrt((double)row_norm(u));
+        if (W256)
+            for (int v = 0; v < 16; ++v) W256[u * 16 + v] = 256 / (row_norm(u) * row_norm(v));
+    }
+    return ADCT_OK;
+}
+
+int adct_quant_tables(int qp, float* qs256, float* dqs256) {
+    Scale5Host q, d;
+    if (!quant_scales(qp, &q, &d)) return ADCT_E_ARG;
+    for (int u = 0; u < 16; ++u)
+        for (int v = 0; v < 16; ++v) {
+            const int c = class_of(u, v);
+            if (qs256) qs256[u * 16 + v] = q.f[c];
+            if (dqs256) dqs256[u * 16 + v] = d.f[c];
+        }
+    return ADCT_OK;
+}
+
+int adct_psnr(const int64_t* sse, int32_t n, double pixels_per_image, double peak, double* out) {
+    if (!sse || !out || n < 0 || !(pixels_per_image > 0) || !(peak > 0)) return ADCT_E_ARG;
+    for (int32_t i = 0; i < n; ++i) {
+        if (sse[i] < 0) return ADCT_E_ARG;
+        out[i] = sse[i] == 0 ? INFINITY : 10.0 * log10(peak * peak * pixels_per_image / (double)sse[i]);
+    }
+    return ADCT_OK;
+}
+
+// Host execution of the kernels' 1D butterflies (the same code the GPU
+// runs), for checking the dataflow without a GPU.
+int adct_host_butterfly(int32_t inverse, const int32_t* in16, int32_t* out16) {
+    if (!in16 || !out16) return ADCT_E_ARG;
+    int32_t x[16], y[16];
+    memcpy(x, in16, sizeof x);
+    if (inverse)
+        inv16(x, y);
+    else
+        fwd16(x, y);
+    memcpy(out16, y, sizeof y);
+    return ADCT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,274 @@
+"""GPU parity: every device entry point against the CPU oracle.
+
+Integer outputs (coefficients, levels, fixed-point coefficients,
+reconstructions, SSE) must be bit-identical.  Float outputs: the orthonormal
+scale within 1e-5 relative of the float64 value; PSNR within 1e-5 relative.
+Quantisation levels are decided in fp32 on both sides (the oracle's
+float32 path), and checked against the float64 decision within the tie band.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import adct_oracle as O
+from oracle import metrics as M
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1606_07414_amd import adct  # noqa: E402
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def padded(a, extra_cols):
+    """Device copy of a plane whose rows carry `extra_cols` samples of padding
+    (filled with a sentinel), as a strided view."""
+    h, w = a.shape
+    buf = np.full((h, w + extra_cols), 77, dtype=a.dtype)
+    buf[:, :w] = a
+    t = dev(buf)
+    return t[:, :w]
+
+
+SHAPES = [(16, 16), (48, 80), (272, 528), (256, 256), (64, 1024)]
+
+
+def extreme_tiles(lo, hi):
+    T = O.transform_matrix()
+    signs = np.einsum("ui,vj->uvij", T, T).reshape(256, 16, 16)
+    return np.concatenate([np.where(signs > 0, hi, lo), np.where(signs < 0, hi, lo)])
+
+
+# ------------------------------------------------------------------ forward
+@pytest.mark.parametrize("shape", SHAPES)
+def test_fwd2d_u8_ar1(shape):
+    img = synth.ar1_image(100 + shape[0], *shape)
+    got = host(adct.fwd2d(dev(img)))
+    assert np.array_equal(got, O.fwd2d(img))
+
+
+def test_fwd2d_u8_structured_and_extremes():
+    tiles = np.concatenate([synth.structured_tiles(), synth.random_binary_tiles(300),
+                            extreme_tiles(0, 255)]).astype(np.uint8)
+    img = synth.tiles_to_plane(tiles, 13)
+    got = host(adct.fwd2d(dev(img)))
+    want = O.fwd2d(img)
+    assert np.array_equal(got, want)
+    assert want[..., 0, 0].max() == 65280 and np.abs(want.reshape(-1, 256)[:, 1:]).max() == 32640
+
+
+def test_fwd2d_u8_pitched():
+    img = synth.ar1_image(7, 64, 96)
+    t = padded(img, 32)
+    assert t.stride(0) == 128
+    assert np.array_equal(host(adct.fwd2d(t)), O.fwd2d(img))
+
+
+@pytest.mark.parametrize("shape", [(16, 16), (48, 80), (544, 960)])
+def test_fwd2d_i16_residual(shape):
+    res = synth.laplacian_residual(200 + shape[0], *shape)
+    assert np.array_equal(host(adct.fwd2d(dev(res))), O.fwd2d(res))
+
+
+def test_fwd2d_i16_extremes_and_full_range():
+    tiles = np.concatenate([extreme_tiles(-255, 255), synth.random_binary_tiles(64, lo=-255, hi=255)])
+    img = synth.tiles_to_plane(tiles.astype(np.int16), 16)
+    want = O.fwd2d(img)
+    assert np.abs(want).max() == 65280
+    assert np.array_equal(host(adct.fwd2d(dev(img))), want)
+    # any int16 input is exact
+    rng = np.random.default_rng(3)
+    full = rng.integers(-32768, 32768, size=(64, 64)).astype(np.int16)
+    assert np.array_equal(host(adct.fwd2d(dev(full))), O.fwd2d(full))
+
+
+# ------------------------------------------------------------------ inverse
+@pytest.mark.parametrize("nblk", [1, 15, 16, 17, 1000])
+def test_inv2d(nblk):
+    rng = np.random.default_rng(nblk)
+    Y = rng.integers(-(1 << 24), 1 << 24, size=(nblk, 16, 16)).astype(np.int32)
+    assert np.array_equal(host(adct.inv2d(dev(Y))), O.inv2d(Y))
+
+
+def test_inverse_then_forward_identity_on_gpu_output():
+    # T (T^T Y T) T^T = D Y D, with the GPU computing T^T Y T
+    T = O.transform_matrix()
+    D = T @ T.T
+    rng = np.random.default_rng(9)
+    Y = rng.integers(-70000, 70000, size=(64, 16, 16)).astype(np.int32)
+    R = host(adct.inv2d(dev(Y))).astype(np.int64)
+    assert np.array_equal(np.einsum("ui,kij,vj->kuv", T, R, T), D[None] @ Y.astype(np.int64) @ D[None])
+
+
+def test_weighted_roundtrip_identity_on_gpu():
+    # T^T (W . T X T^T) T = 256 X: r = 16 zonal reconstruction is lossless
+    img = synth.ar1_image(1, 256, 256)
+    x = dev(img)
+    coef = adct.fwd2d(x)
+    out = torch.empty_like(x)
+    s = adct.zonal_recon(coef, 16, out, ref=x)
+    assert np.array_equal(host(out), img)
+    assert host(s)[0] == 0
+    zfix = adct.zonal(coef, 16)
+    R = O.inv2d(host(zfix))
+    assert np.array_equal(R, 256 * O.to_tiles(img.astype(np.int64)))
+
+
+# ------------------------------------------------------------------ scale / quant
+def test_scale_relative_error():
+    img = synth.ar1_image(1, 256, 256)
+    coef = adct.fwd2d(dev(img))
+    got = host(adct.scale(coef)).astype(np.float64)
+    want = O.scale(O.fwd2d(img))
+    nz = want != 0
+    assert np.all(got[~nz] == 0)
+    assert np.max(np.abs(got[nz] - want[nz]) / np.abs(want[nz])) < 1e-5
+
+
+def test_s_scaled_psnr_vs_exact_dct():
+    # single 256x256 image: PSNR of the S-scaled coefficients against the
+    # float64 exact DCT, GPU coefficients vs oracle coefficients
+    img = synth.ar1_image(1, 256, 256)
+    B_gpu = host(adct.scale(adct.fwd2d(dev(img)))).astype(np.float64)
+    B_ref = M.exact_dct2d_tiles(O.to_tiles(img))
+    p_gpu = M.coefficient_psnr(B_gpu, B_ref)
+    p_orc = M.coefficient_psnr(O.scale(O.fwd2d(img)), B_ref)
+    assert p_gpu == pytest.approx(p_orc, rel=1e-5)
+    assert 20 < p_orc < 30
+
+
+@pytest.mark.parametrize("qp", [4, 22, 27, 32, 37, 51])
+def test_quant_and_dequant(qp):
+    res = synth.laplacian_residual(300 + qp, 128, 256)
+    Y = O.fwd2d(res)
+    coef = dev(Y.astype(np.int32))
+    q = host(adct.quant(coef, qp))
+    want = O.quantise(Y, qp)
+    assert np.array_equal(q, want)
+    q64, v = O.quantise_fp64(Y, qp)
+    diff = q != q64
+    band = np.abs(np.abs(v) - np.floor(np.abs(v)) - 0.5) <= 2.0 ** -20 * np.maximum(np.abs(v), 1)
+    assert np.all(band[diff])
+    z = host(adct.dequant(dev(q), qp))
+    assert np.array_equal(z, O.dequantise(want, qp))
+
+
+def test_quant_saturates_to_int16():
+    Y = np.zeros((1, 16, 16), np.int32)
+    Y[0, 0, 0] = 2_000_000_000
+    Y[0, 2, 2] = -2_000_000_000
+    q = host(adct.quant(dev(Y), 0))
+    assert q[0, 0, 0] == 32767 and q[0, 2, 2] == -32768
+
+
+@pytest.mark.parametrize("r", [0, 1, 2, 4, 8, 12, 16])
+def test_zonal_and_recon(r):
+    img = synth.ar1_image(400 + r, 48, 80)
+    Y = O.fwd2d(img)
+    z = host(adct.zonal(dev(Y.astype(np.int32)), r))
+    assert np.array_equal(z, O.zonal(Y, r))
+    out = torch.empty((48, 80), dtype=torch.uint8, device="cuda")
+    adct.recon(dev(z), out)
+    want = O.from_tiles(O.round_clamp(O.reconstruct_fixed(z), 0, 255), 48, 80)
+    assert np.array_equal(host(out), want)
+
+
+# ------------------------------------------------------------------ fused paths
+@pytest.mark.parametrize("r", [0, 1, 2, 4, 8, 12, 16])
+@pytest.mark.parametrize("shape,image_h", [((256, 256), 256), ((272, 528), 272), ((96, 48), 32), ((1024, 512), 512)])
+def test_zonal_recon_with_sse(r, shape, image_h):
+    img = synth.ar1_batch(shape[0] // image_h, image_h, shape[1], seed_base=500 + r)
+    x = dev(img)
+    coef = adct.fwd2d(x)
+    out = torch.empty_like(x)
+    s = host(adct.zonal_recon(coef, r, out, ref=x, image_height=image_h))
+    want = O.zonal_reconstruct(img, r)
+    assert np.array_equal(host(out), want)
+    for i in range(shape[0] // image_h):
+        assert s[i] == O.sse(want[i * image_h:(i + 1) * image_h], img[i * image_h:(i + 1) * image_h])
+
+
+def test_zonal_recon_without_sse_and_pitched_output():
+    img = synth.ar1_image(31, 64, 96)
+    coef = adct.fwd2d(dev(img))
+    out = padded(np.zeros_like(img), 32)
+    adct.zonal_recon(coef, 4, out)
+    got = host(out.contiguous())
+    assert np.array_equal(got, O.zonal_reconstruct(img, 4))
+    # padding untouched
+    assert np.all(host(out.as_strided((64, 32), (128, 1), out.storage_offset() + 96)) == 77)
+
+
+@pytest.mark.parametrize("qp", [22, 27, 32, 37])
+@pytest.mark.parametrize("shape", [(544, 960), (48, 80)])
+def test_fwd2d_quant_dequant_recon(qp, shape):
+    res = synth.laplacian_residual(600 + qp, *shape)
+    x = dev(res)
+    q = adct.fwd2d_quant(x, qp)
+    q_want = O.quantise(O.fwd2d(res), qp)
+    assert np.array_equal(host(q), q_want)
+    out = torch.empty_like(x)
+    s = host(adct.dequant_recon(q, qp, out, ref=x))
+    _, z, want = O.quant_reconstruct(res, qp)
+    assert np.array_equal(host(out), want)
+    assert s[0] == O.sse(want, res)
+
+
+def test_dequant_recon_u8():
+    img = synth.ar1_image(44, 64, 64)
+    q = adct.fwd2d_quant(dev(img), 27)
+    out = torch.empty((64, 64), dtype=torch.uint8, device="cuda")
+    adct.dequant_recon(q, 27, out)
+    z = O.dequantise(O.quantise(O.fwd2d(img), 27), 27)
+    want = O.from_tiles(O.round_clamp(O.reconstruct_fixed(z), 0, 255), 64, 64)
+    assert np.array_equal(host(out), want)
+
+
+@pytest.mark.parametrize("dtype", [np.uint8, np.int16])
+def test_sse(dtype):
+    rng = np.random.default_rng(5)
+    lo, hi = (0, 256) if dtype == np.uint8 else (-255, 256)
+    a = rng.integers(lo, hi, size=(480, 64)).astype(dtype)
+    b = rng.integers(lo, hi, size=(480, 64)).astype(dtype)
+    s = host(adct.sse(dev(a), dev(b), image_height=160))
+    for i in range(3):
+        assert s[i] == O.sse(a[i * 160:(i + 1) * 160], b[i * 160:(i + 1) * 160])
+
+
+def test_psnr_from_gpu_sse_matches_oracle():
+    img = synth.ar1_image(1, 256, 256)
+    x = dev(img)
+    out = torch.empty_like(x)
+    s = host(adct.zonal_recon(adct.fwd2d(x), 8, out, ref=x))
+    p = adct.psnr(s, img.size)[0]
+    want = O.psnr(O.sse(O.zonal_reconstruct(img, 8), img), img.size)
+    assert p == pytest.approx(want, rel=1e-12)
+
+
+def test_repeat_runs_identical():
+    img = synth.ar1_batch(4, 256, 256, seed_base=70)
+    x = dev(img)
+    outs = []
+    for _ in range(3):
+        c = adct.fwd2d(x)
+        o = torch.empty_like(x)
+        s = adct.zonal_recon(c, 8, o, ref=x, image_height=256)
+        outs.append((host(c).tobytes(), host(o).tobytes(), host(s).tobytes()))
+    assert outs[0] == outs[1] == outs[2]
+
+
+def test_errors_raise_without_launch():
+    x = torch.zeros((24, 16), dtype=torch.uint8, device="cuda")
+    with pytest.raises(adct.AdctError) as e:
+        adct.fwd2d(x)
+    assert e.value.code == adct.E_SHAPE
