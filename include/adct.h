@@ -108,8 +108,11 @@ int adct_host_butterfly(int32_t inverse, const int32_t* in16, int32_t* out16);
 /* Forward transform Y = T A T^T of every 16x16 block of `src` (Section 3.1;
  * each 1D pass by the Section 2.2 factorisation, 44 additions).
  * src: U8 or I16 plane.  coef: device int32 [nblk][16][16].
- * Exact (bit-identical to the integer matrix product): |Y| <= 65280 for U8
- * samples and for I16 samples within [-255, 255]; any I16 input is exact. */
+ * Exact (bit-identical to the integer matrix product) for every U8 input
+ * (|Y| <= 65280) and for I16 samples within [-2047, 2047] (the row pass runs
+ * in 16-bit lanes); I16 samples outside that range give unspecified
+ * coefficients.  The same range rule holds for every call taking an I16
+ * source plane. */
 int adct_fwd2d(const adct_plane* src, int32_t* coef, void* stream);
 
 /* Plain inverse R = T^T Y T of `nblk` blocks (Section 3.1, without S).
@@ -172,6 +175,25 @@ int adct_zonal_recon(const int32_t* coef, int r, const adct_plane* dst,
 int adct_dequant_recon(const int16_t* q, int qp, const adct_plane* dst,
                        const adct_plane* ref, int32_t image_height, int64_t* sse,
                        void* stream);
+
+/* Single-pass encoder with reconstruction, zonal form (Section 3.1's
+ * experiment): per block Y = T A T^T, optionally stored to `coef` (as
+ * adct_fwd2d; NULL skips the store), then zonal retention of the top-left
+ * r x r coefficients with S folded in, the inverse, rounding and clamping
+ * into `dst` (same shape and type as src), and -- when `sse` is non-NULL --
+ * the exact per-image SSE of dst against src for images of `image_height`
+ * rows.  Bit-identical to adct_fwd2d + adct_zonal_recon; reads src once.
+ * r in [0, 16].  sse: device int64 [height / image_height], overwritten. */
+int adct_encode_zonal(const adct_plane* src, int r, int32_t* coef, const adct_plane* dst,
+                      int32_t image_height, int64_t* sse, void* stream);
+
+/* Single-pass encoder with reconstruction, quantised form (Section 3.2's
+ * use, S folded into the quantiser): levels q as adct_fwd2d_quant, stored to
+ * `q` unless NULL, then dequantisation, inverse, rounding and clamping into
+ * `dst`, and the optional per-image SSE against src.  Bit-identical to
+ * adct_fwd2d_quant + adct_dequant_recon. */
+int adct_encode_quant(const adct_plane* src, int qp, int16_t* q, const adct_plane* dst,
+                      int32_t image_height, int64_t* sse, void* stream);
 
 #ifdef __cplusplus
 }

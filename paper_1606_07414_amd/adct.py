@@ -54,6 +54,8 @@ _SIGNATURES = {
     "adct_fwd2d_quant": (ctypes.c_int, [_PP, ctypes.c_int, _P, _P]),
     "adct_zonal_recon": (ctypes.c_int, [_P, ctypes.c_int, _PP, _PP, _I32, _P, _P]),
     "adct_dequant_recon": (ctypes.c_int, [_P, ctypes.c_int, _PP, _PP, _I32, _P, _P]),
+    "adct_encode_zonal": (ctypes.c_int, [_PP, ctypes.c_int, _P, _PP, _I32, _P, _P]),
+    "adct_encode_quant": (ctypes.c_int, [_PP, ctypes.c_int, _P, _PP, _I32, _P, _P]),
 }
 
 _LIB = None
@@ -259,6 +261,34 @@ def dequant_recon(q, qp: int, dst, ref=None, image_height=None, sse=None, stream
     rp, ih, sse, sp = _ref_args(ref, image_height, sse, dst)
     _check(_lib().adct_dequant_recon(q.data_ptr(), qp, ctypes.byref(p), ctypes.byref(rp) if rp else None,
                                      ih, sp, _stream(stream)), "dequant_recon")
+    return sse
+
+
+def _sse_out(src, image_height, sse, want):
+    torch = _torch()
+    if not want:
+        return 0, None, None
+    if image_height is None:
+        image_height = src.shape[0]
+    if sse is None:
+        sse = torch.empty(src.shape[0] // image_height, dtype=torch.int64, device=src.device)
+    return image_height, sse, sse.data_ptr()
+
+
+def encode_zonal(src, r: int, dst, coef=None, image_height=None, sse=None, want_sse=True, stream=None):
+    """Returns the per-image SSE tensor (or None when want_sse is False)."""
+    ps, pd = plane(src), plane(dst)
+    ih, sse, sp = _sse_out(src, image_height, sse, want_sse)
+    _check(_lib().adct_encode_zonal(ctypes.byref(ps), r, coef.data_ptr() if coef is not None else None,
+                                    ctypes.byref(pd), ih, sp, _stream(stream)), "encode_zonal")
+    return sse
+
+
+def encode_quant(src, qp: int, dst, q=None, image_height=None, sse=None, want_sse=True, stream=None):
+    ps, pd = plane(src), plane(dst)
+    ih, sse, sp = _sse_out(src, image_height, sse, want_sse)
+    _check(_lib().adct_encode_quant(ctypes.byref(ps), qp, q.data_ptr() if q is not None else None,
+                                    ctypes.byref(pd), ih, sp, _stream(stream)), "encode_quant")
     return sse
 
 

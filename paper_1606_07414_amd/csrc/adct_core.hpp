@@ -1,0 +1,611 @@
+// The tile-group processor: every device entry point is one configuration
+// of `process_group`, either launched one group per workgroup (plain calls)
+// or called in a loop by a persistent workgroup (batches, serving).
+//
+// A group is TPW tiles of one plane, consecutive in raster order.  It is
+// processed by 8 * TPW threads; each thread owns two sample rows (i, i+8) of
+// one tile in the "row role" and two coefficient columns (p, p+8) of one
+// tile in the "column role":
+//
+//   row role     lt = tid % TPW, ip = tid / TPW   (lanes of consecutive lt
+//                read/write horizontally adjacent 16-sample segments)
+//   column role  lt = tid / 8,   p  = tid % 8     (lanes of consecutive p
+//                touch adjacent coefficients)
+//
+// Forward (Section 3.1, Y = T A T^T, each 1D pass the Section 2.2 dataflow):
+//   row pass     the two rows are packed as 16-bit pairs and transformed
+//                together with packed 16-bit add/sub (one instruction = two
+//                rows); results go to LDS as (column p, column p+8) pairs;
+//   column pass  the two columns are again one packed pair.  For uint8
+//                input every forward quantity is exact modulo 2^16: DC lies
+//                in [0, 65280] and every other coefficient in
+//                [-32640, 32640], so the 16-bit results are widened by zero
+//                extension (DC) or sign extension (the rest).  int16
+//                residuals (|Y| up to 65280 anywhere) widen after the row
+//                pass and run the column pass in int32.
+// Coefficient domain (registers, columns p and p+8): int32 coefficients,
+//   quantisation with S folded into the step (Section 2.1), dequantisation to
+//   8 fractional bits, or zonal retention with W = 256/(d_u d_v).
+// Inverse (Section 3.1, T^T Z' T): column pass in int32, LDS transpose, row
+//   pass, rounding floor((R + 128) / 256) and clamping.  The +128 is added
+//   once per tile to Z'[0][0]: T^T e0 e0^T T is the all-ones matrix, so it
+//   reaches every sample.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "adct_butterfly.hpp"
+#include "adct_tile.hpp"
+
+namespace adct {
+
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ u16x2 as_u16x2(uint32_t w) { return __builtin_bit_cast(u16x2, w); }
+__device__ __forceinline__ uint32_t as_u32(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
+__device__ __forceinline__ int32_t sext_lo(uint32_t w) { return (int32_t)(int16_t)(w & 0xffffu); }
+__device__ __forceinline__ int32_t sext_hi(uint32_t w) { return (int32_t)w >> 16; }
+__device__ __forceinline__ uint32_t perm(uint32_t hi_src, uint32_t lo_src, uint32_t sel) {
+    return __builtin_amdgcn_perm(hi_src, lo_src, sel);
+}
+
+// LDS geometry (32-bit words).  Forward pairs: [tile][row k][pair p], 8
+// words per row; int32 blocks: [tile][row][col], 16 words per row.  Both
+// tile strides are 8 (mod 32) so that the lanes of a column-role access hit
+// distinct banks.
+constexpr int kPairTile = 16 * 8 + 8;   // 136
+constexpr int kIntRow = 16;
+constexpr int kIntTile = 16 * 16 + 8;   // 264
+constexpr int lds_words(int tpw) { return tpw * kIntTile; }
+
+enum InKind { kInSamples = 0, kInY = 1, kInZfix = 2, kInQ = 3 };
+enum CStore { kStoreNone = 0, kStoreY = 1, kStoreQ = 2 };
+enum Mid { kMidNone = 0, kMidZonal = 1, kMidQuant = 2, kMidDequant = 3 };
+enum OutKind { kOutNothing = 0, kOutSamples = 1, kOutBlocks = 2 };
+
+template <int IN_, int STORE_, int MID_, int OUT_, int ZR_, bool SSE_>
+struct Mode {
+    static constexpr int IN = IN_, STORE = STORE_, MID = MID_, OUT = OUT_, ZR = ZR_;
+    static constexpr bool SSE = SSE_;
+};
+
+// One group's location and the call's parameters.
+struct GroupArgs {
+    PlaneRef src;            // samples in (kInSamples)
+    PlaneRef dst;            // samples out (kOutSamples)
+    PlaneRef ref;            // SSE reference when samples are not the input
+    const void* cin;         // coefficient-domain input, block-major
+    void* cout;              // int32 Y or int16 q out, block-major
+    int32_t* bout;           // int32 blocks out (kOutBlocks)
+    int32_t r;               // zonal size when not fixed at compile time
+    Scale5 qs, dqs;          // quantiser / dequantiser per class
+    uint32_t bw;             // tiles per row of every plane of the call
+    FastDiv bwdiv;           // division by bw
+    FastDiv ipbdiv;          // division by tile rows per image (SSE image index)
+    unsigned long long* sse; // per-image SSE accumulators
+};
+
+// ---- sample rows as 16-bit pairs ------------------------------------------------
+// Rows ip and ip+8 of a tile, raw words (uint8: 16 samples in a0; int16: 8
+// samples each in a0, a1; likewise b for row ip+8), as 16 packed pairs
+// (row ip sample k, row ip+8 sample k): uint8 zero-extended, int16 as is.
+template <typename S>
+__device__ __forceinline__ void pack_rows(uint4 a0, uint4 a1, uint4 b0, uint4 b1, uint32_t (&xk)[16]) {
+    if constexpr (sizeof(S) == 1) {
+        const uint32_t a[4] = {a0.x, a0.y, a0.z, a0.w}, b[4] = {b0.x, b0.y, b0.z, b0.w};
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const uint32_t m = (uint32_t)(k & 3);
+            xk[k] = perm(b[k >> 2], a[k >> 2], 0x0c000c00u | ((4u + m) << 16) | m);
+        }
+    } else {
+        const uint32_t a[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+        const uint32_t b[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
+#pragma unroll
+        for (int k = 0; k < 16; ++k) xk[k] = perm(b[k >> 1], a[k >> 1], (k & 1) ? 0x07060302u : 0x05040100u);
+    }
+}
+
+// Address of sample row `row` of the tile at tile-row by, tile-column bx.
+template <typename S>
+__device__ __forceinline__ const char* row_ptr(const PlaneRef& pl, uint32_t by, uint32_t bx, int row) {
+    return pl.data + (int64_t)(by * 16u + (uint32_t)row) * pl.pitch + (int64_t)bx * (16 * (int64_t)sizeof(S));
+}
+
+// Loads rows ip and ip+8 of tile (by, bx) (zeros when !ok) as raw words.
+template <typename S>
+__device__ __forceinline__ void load_rows(const PlaneRef& pl, uint32_t by, uint32_t bx, bool ok, int ip, uint4& a0,
+                                          uint4& a1, uint4& b0, uint4& b1) {
+    a0 = a1 = b0 = b1 = make_uint4(0, 0, 0, 0);
+    if (ok) {
+        const char* pa = row_ptr<S>(pl, by, bx, ip);
+        const char* pb = pa + 8 * pl.pitch;
+        a0 = reinterpret_cast<const uint4*>(pa)[0];
+        b0 = reinterpret_cast<const uint4*>(pb)[0];
+        if constexpr (sizeof(S) == 2) {
+            a1 = reinterpret_cast<const uint4*>(pa)[1];
+            b1 = reinterpret_cast<const uint4*>(pb)[1];
+        }
+    }
+}
+
+// Exact SSE of the two output rows r0, r1 (values in the sample range)
+// against packed input pairs: 16-bit differences, squared and accumulated
+// two at a time by v_dot2_i32_i16.
+__device__ __forceinline__ int32_t pair_sse(const int32_t (&r0)[16], const int32_t (&r1)[16],
+                                            const uint32_t (&xk)[16]) {
+    typedef short s16x2 __attribute__((ext_vector_type(2)));
+    int32_t s = 0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const uint32_t o = perm((uint32_t)r1[j], (uint32_t)r0[j], 0x05040100u);
+        const s16x2 d = __builtin_bit_cast(s16x2, o) - __builtin_bit_cast(s16x2, xk[j]);
+        s = __builtin_amdgcn_sdot2(d, d, s, false);
+    }
+    return s;
+}
+
+// ---- forward row pass (row role) -------------------------------------------
+// Loads rows ip and ip+8 of tile g and leaves the packed row-pass output in
+// LDS pairs.  `xk` keeps the packed input samples for the SSE.
+// Raw sample words of rows ip and ip+8 of one tile (row role).
+struct RowWords {
+    uint4 a0, a1, b0, b1;
+};
+
+template <typename S>
+__device__ __forceinline__ void fwd_rows(const RowWords& w, int lt, int ip, uint32_t* lds, uint32_t (&xk)[16]) {
+    pack_rows<S>(w.a0, w.a1, w.b0, w.b1, xk);
+    u16x2 x[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) x[k] = as_u16x2(xk[k]);
+    u16x2 z[16];
+    fwd16(x, z);
+    uint32_t w0[8], w1[8];
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+        w0[p] = perm(as_u32(z[p + 8]), as_u32(z[p]), 0x05040100u);  // row ip:   (Z[ip][p], Z[ip][p+8])
+        w1[p] = perm(as_u32(z[p + 8]), as_u32(z[p]), 0x07060302u);  // row ip+8
+    }
+    uint4* l0 = reinterpret_cast<uint4*>(lds + lt * kPairTile + ip * 8);
+    uint4* l1 = reinterpret_cast<uint4*>(lds + lt * kPairTile + (ip + 8) * 8);
+    l0[0] = make_uint4(w0[0], w0[1], w0[2], w0[3]);
+    l0[1] = make_uint4(w0[4], w0[5], w0[6], w0[7]);
+    l1[0] = make_uint4(w1[0], w1[1], w1[2], w1[3]);
+    l1[1] = make_uint4(w1[4], w1[5], w1[6], w1[7]);
+}
+
+// ---- forward column pass (column role) ------------------------------------
+// ya[u] = Y[u][p], yb[u] = Y[u][p+8] as int32.
+template <typename S>
+__device__ __forceinline__ void fwd_columns(const uint32_t* lds, int lt, int p, int32_t (&ya)[16],
+                                            int32_t (&yb)[16]) {
+    uint32_t w[16];
+    const uint32_t* l = lds + lt * kPairTile + p;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) w[k] = l[k * 8];
+    if constexpr (sizeof(S) == 1) {
+        u16x2 z[16], y[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) z[k] = as_u16x2(w[k]);
+        fwd16(z, y);
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const uint32_t t = as_u32(y[u]);
+            ya[u] = sext_lo(t);
+            yb[u] = sext_hi(t);
+        }
+        // the DC coefficient is the only one outside the signed 16-bit range
+        if (p == 0) ya[0] = (int32_t)(as_u32(y[0]) & 0xffffu);
+    } else {
+        int32_t za[16], zb[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            za[k] = sext_lo(w[k]);
+            zb[k] = sext_hi(w[k]);
+        }
+        fwd16(za, ya);
+        fwd16(zb, yb);
+    }
+}
+
+// ---- int32 block staging through LDS --------------------------------------
+// Column role writes columns p and p+8 of a 16x16 int32 block.
+__device__ __forceinline__ void lds_put_columns(uint32_t* lds, int lt, int p, const int32_t (&a)[16],
+                                                const int32_t (&b)[16]) {
+    int32_t* l = reinterpret_cast<int32_t*>(lds) + lt * kIntTile + p;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        l[u * kIntRow] = a[u];
+        l[u * kIntRow + 8] = b[u];
+    }
+}
+
+// Row role reads row i of the block.
+__device__ __forceinline__ void lds_get_row(const uint32_t* lds, int lt, int i, int32_t (&r)[16]) {
+    const int4* l = reinterpret_cast<const int4*>(lds + lt * kIntTile + i * kIntRow);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int4 w = l[k];
+        r[4 * k] = w.x;
+        r[4 * k + 1] = w.y;
+        r[4 * k + 2] = w.z;
+        r[4 * k + 3] = w.w;
+    }
+}
+
+// Whole group: contiguous [ntile][16][16] int32 <-> LDS, 16-byte chunks,
+// chunk c of the group = tile c/64, row (c/4)%16, column 4*(c%4).
+template <int TPW>
+__device__ __forceinline__ void lds_blocks_to_global(const uint32_t* lds, int tid, uint32_t ntile,
+                                                     int32_t* out) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int c = tid + k * TPW * 8;
+        const int t = c >> 6, u = (c >> 2) & 15, v4 = c & 3;
+        if ((uint32_t)t < ntile)
+            store16(reinterpret_cast<uint4*>(out) + c,
+                    *reinterpret_cast<const uint4*>(lds + t * kIntTile + u * kIntRow + 4 * v4));
+    }
+}
+
+// int16 blocks: chunk c (8 coefficients) = tile c/32, row (c/2)%16, half c%2.
+template <int TPW>
+__device__ __forceinline__ void lds_q_to_global(const uint32_t* lds, int tid, uint32_t ntile, int16_t* out) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int c = tid + k * TPW * 8;
+        const int t = c >> 5, u = (c >> 1) & 15, h = c & 1;
+        if ((uint32_t)t < ntile)
+            store16(reinterpret_cast<uint4*>(out) + c,
+                    *reinterpret_cast<const uint4*>(lds + t * kIntTile + u * kIntRow + 4 * h));
+    }
+}
+
+// Column role writes int16 columns p, p+8 into the [tile][u][8 words] layout.
+__device__ __forceinline__ void lds_put_q_columns(uint32_t* lds, int lt, int p, const int32_t (&qa)[16],
+                                                  const int32_t (&qb)[16]) {
+    int16_t* l = reinterpret_cast<int16_t*>(lds + lt * kIntTile) + p;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        l[u * 2 * kIntRow] = (int16_t)qa[u];
+        l[u * 2 * kIntRow + 8] = (int16_t)qb[u];
+    }
+}
+
+template <int TPW>
+__device__ __forceinline__ void global_blocks_to_lds(const int32_t* in, int tid, uint32_t ntile, int rows,
+                                                     int cols4, uint32_t* lds) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int c = tid + k * TPW * 8;
+        const int t = c >> 6, u = (c >> 2) & 15, v4 = c & 3;
+        int4 w = make_int4(0, 0, 0, 0);
+        if ((uint32_t)t < ntile && u < rows && v4 < cols4) w = reinterpret_cast<const int4*>(in)[c];
+        *reinterpret_cast<int4*>(lds + t * kIntTile + u * kIntRow + 4 * v4) = w;
+    }
+}
+
+template <int TPW>
+__device__ __forceinline__ void global_q_to_lds(const int16_t* in, int tid, uint32_t ntile, uint32_t* lds) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int c = tid + k * TPW * 8;
+        const int t = c >> 5, u = (c >> 1) & 15, h = c & 1;
+        uint4 w = make_uint4(0, 0, 0, 0);
+        if ((uint32_t)t < ntile) w = reinterpret_cast<const uint4*>(in)[c];
+        *reinterpret_cast<uint4*>(lds + t * kIntTile + u * kIntRow + 4 * h) = w;
+    }
+}
+
+// Column role reads int32 columns p, p+8 (rows u < rows; others zero).
+__device__ __forceinline__ void lds_get_columns(const uint32_t* lds, int lt, int p, int32_t (&a)[16],
+                                                int32_t (&b)[16]) {
+    const int32_t* l = reinterpret_cast<const int32_t*>(lds) + lt * kIntTile + p;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        a[u] = l[u * kIntRow];
+        b[u] = l[u * kIntRow + 8];
+    }
+}
+
+__device__ __forceinline__ void lds_get_q_columns(const uint32_t* lds, int lt, int p, int32_t (&a)[16],
+                                                  int32_t (&b)[16]) {
+    const int16_t* l = reinterpret_cast<const int16_t*>(lds + lt * kIntTile) + p;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        a[u] = l[u * 2 * kIntRow];
+        b[u] = l[u * 2 * kIntRow + 8];
+    }
+}
+
+// ---- coefficient domain ----------------------------------------------------
+// Zonal retention with the S weights; r fixed at compile time (ZR >= 0) or
+// at run time.
+template <int ZR>
+__device__ __forceinline__ void zonal_weights_cols(int p, int rr, int32_t (&a)[16], int32_t (&b)[16]) {
+    const int r = ZR >= 0 ? ZR : rr;
+    const int la = log2_norm(p), lb = log2_norm(p + 8);
+    const bool ka = p < r, kb = p + 8 < r;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const bool ku = ZR >= 0 ? (u < ZR) : (u < r);
+        const int su = 8 - log2_norm(u);
+        a[u] = (ku && ka) ? (int32_t)((uint32_t)a[u] << (su - la)) : 0;
+        b[u] = (ku && kb) ? (int32_t)((uint32_t)b[u] << (su - lb)) : 0;
+    }
+}
+
+__device__ __forceinline__ void quant_cols(const Scale5& qs, int p, const int32_t (&a)[16], const int32_t (&b)[16],
+                                           int32_t (&qa)[16], int32_t (&qb)[16]) {
+    float fa[3], fb[3];
+    column_factors(qs, p, fa);
+    column_factors(qs, p + 8, fb);
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        qa[u] = clamp_i32(round_away(__fmul_rn((float)a[u], fa[log2_norm(u) - 2])), -32768, 32767);
+        qb[u] = clamp_i32(round_away(__fmul_rn((float)b[u], fb[log2_norm(u) - 2])), -32768, 32767);
+    }
+}
+
+__device__ __forceinline__ void dequant_cols(const Scale5& dqs, int p, int32_t (&a)[16], int32_t (&b)[16]) {
+    float fa[3], fb[3];
+    column_factors(dqs, p, fa);
+    column_factors(dqs, p + 8, fb);
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        a[u] = round_away(__fmul_rn((float)a[u], fa[log2_norm(u) - 2]));
+        b[u] = round_away(__fmul_rn((float)b[u], fb[log2_norm(u) - 2]));
+    }
+}
+
+// ---- inverse ---------------------------------------------------------------
+// Rounded, clamped sample: floor(R / 256) within [lo, hi] (R already holds
+// the +128).  Clamping before the shift keeps the compiler from forming
+// v_ashr_pk_u8_i32, whose upper result bits are not cleared before they are
+// OR-ed with the other bytes of a packed row.
+template <typename S>
+__device__ __forceinline__ int32_t out_sample(int32_t R) {
+    return clamp_i32(R, Samples<S>::kLo * 256, Samples<S>::kHi * 256 + 255) >> 8;
+}
+
+template <typename S>
+__device__ __forceinline__ void store_row(char* p, const int32_t (&o)[16]) {
+    Samples<S>::store(p, o);
+}
+
+// ---- per-image SSE accumulated across the groups of a workgroup ------------
+constexpr uint32_t kNoImage = 0xffffffffu;
+
+struct SseAcc {
+    int32_t s;     // this thread's running sum for image `img`
+    uint32_t img;  // image of the running sum (uniform over the workgroup)
+};
+
+__device__ __forceinline__ long long wave_sum64(long long v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Adds the workgroup's running sum to sse[img] with one atomic.  Called with
+// uniform control flow.
+template <int NTHREADS>
+__device__ __forceinline__ void sse_flush(const SseAcc& acc, unsigned long long* sse, long long* red) {
+    if (acc.img == kNoImage) return;
+    const long long v = wave_sum64((long long)acc.s);
+    const int tid = threadIdx.x;
+    __syncthreads();  // a previous flush has finished reading `red`
+    if ((tid & 63) == 0) red[tid >> 6] = v;
+    __syncthreads();
+    if (tid == 0) {
+        long long t = 0;
+#pragma unroll
+        for (int w = 0; w < NTHREADS / 64; ++w) t += red[w];
+        if (t) atomicAdd(sse + acc.img, (unsigned long long)t);
+    }
+}
+
+// ---- the group ----------------------------------------------------------------
+// Processes tiles g0 .. g0 + ntile - 1 (ntile <= TPW) of one plane.  Per-image
+// SSE contributions go to sse[img(tile)] with img = tile_row / ipb.
+// Row-role sample words of group (g0, ntile), for the forward input.
+template <int TPW, typename S>
+__device__ __forceinline__ void load_group_rows(const GroupArgs& a, uint32_t g0, uint32_t ntile, RowWords& w) {
+    const int rlt = threadIdx.x % TPW, rip = threadIdx.x / TPW;
+    const uint32_t rg = g0 + (uint32_t)rlt;
+    const uint32_t rby = fdiv(rg, a.bwdiv), rbx = rg - rby * a.bw;
+    load_rows<S>(a.src, rby, rbx, (uint32_t)rlt < ntile, rip, w.a0, w.a1, w.b0, w.b1);
+}
+
+// `rows` holds this group's input rows (forward modes); once they are
+// consumed, the rows of the next group (g0n, ntn; ntn = 0 for none) are
+// requested into it, so their latency overlaps this group's remaining work.
+template <int TPW, typename S, typename M>
+__device__ __forceinline__ void process_group(const GroupArgs& a, uint32_t g0, uint32_t ntile,
+                                              uint32_t* lds, long long* red, SseAcc& acc, RowWords& rows,
+                                              uint32_t g0n, uint32_t ntn) {
+    const int tid = threadIdx.x;
+    const int rlt = tid % TPW, rip = tid / TPW;     // row role
+    const int clt = tid >> 3, cp = tid & 7;         // column role
+    const bool rok = (uint32_t)rlt < ntile;
+    const uint32_t rg = g0 + (uint32_t)rlt;
+    const uint32_t rby = fdiv(rg, a.bwdiv), rbx = rg - rby * a.bw;  // tile position (row role)
+
+    uint32_t xk[16];   // packed input or reference samples (row role), for the SSE
+    uint4 ra0, ra1, rb0, rb1;
+    int32_t ya[16], yb[16];
+
+    // ---------------- input --------------------------------------------------
+    if constexpr (M::IN == kInSamples) {
+        fwd_rows<S>(rows, rlt, rip, lds, xk);
+        if (ntn) load_group_rows<TPW, S>(a, g0n, ntn, rows);
+        __syncthreads();
+        fwd_columns<S>(lds, clt, cp, ya, yb);
+    } else {
+        if constexpr (M::SSE) {
+            // prefetch the reference rows so their latency overlaps the rest
+            load_rows<S>(a.ref, rby, rbx, rok, rip, ra0, ra1, rb0, rb1);
+        }
+        if constexpr (M::IN == kInQ) {
+            global_q_to_lds<TPW>(static_cast<const int16_t*>(a.cin) + (int64_t)g0 * 256, tid, ntile, lds);
+            __syncthreads();
+            lds_get_q_columns(lds, clt, cp, ya, yb);
+        } else {
+            int rows = 16, cols4 = 4;
+            if constexpr (M::MID == kMidZonal) {
+                const int r = M::ZR >= 0 ? M::ZR : a.r;
+                rows = r;
+                cols4 = (r + 3) >> 2;
+            }
+            global_blocks_to_lds<TPW>(static_cast<const int32_t*>(a.cin) + (int64_t)g0 * 256, tid, ntile,
+                                      rows, cols4, lds);
+            __syncthreads();
+            lds_get_columns(lds, clt, cp, ya, yb);
+        }
+    }
+
+    // ---------------- coefficient domain ----------------------------------------
+    if constexpr (M::STORE == kStoreY) {
+        __syncthreads();
+        lds_put_columns(lds, clt, cp, ya, yb);
+        __syncthreads();
+        lds_blocks_to_global<TPW>(lds, tid, ntile, static_cast<int32_t*>(a.cout) + (int64_t)g0 * 256);
+    }
+    if constexpr (M::MID == kMidQuant) {
+        int32_t qa[16], qb[16];
+        quant_cols(a.qs, cp, ya, yb, qa, qb);
+        if constexpr (M::STORE == kStoreQ) {
+            __syncthreads();
+            lds_put_q_columns(lds, clt, cp, qa, qb);
+            __syncthreads();
+            lds_q_to_global<TPW>(lds, tid, ntile, static_cast<int16_t*>(a.cout) + (int64_t)g0 * 256);
+        }
+        if constexpr (M::OUT != kOutNothing) {
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                ya[u] = qa[u];
+                yb[u] = qb[u];
+            }
+            dequant_cols(a.dqs, cp, ya, yb);
+        }
+    } else if constexpr (M::MID == kMidDequant) {
+        dequant_cols(a.dqs, cp, ya, yb);
+    } else if constexpr (M::MID == kMidZonal) {
+        zonal_weights_cols<M::ZR>(cp, a.r, ya, yb);
+    }
+
+    if constexpr (M::OUT == kOutNothing) return;
+
+    // ---------------- inverse ------------------------------------------------------
+    if constexpr (M::OUT == kOutSamples) {
+        if (cp == 0) ya[0] += 128;  // rounding offset, reaches every sample
+    }
+    {
+        int32_t qa[16], qb[16];
+        inv16(ya, qa);
+        inv16(yb, qb);
+        __syncthreads();
+        lds_put_columns(lds, clt, cp, qa, qb);
+        __syncthreads();
+    }
+    int32_t r0[16], r1[16];
+    {
+        int32_t q[16];
+        lds_get_row(lds, rlt, rip, q);
+        inv16(q, r0);
+        lds_get_row(lds, rlt, rip + 8, q);
+        inv16(q, r1);
+    }
+    if constexpr (M::OUT == kOutBlocks) {
+        if (rok) {
+            int4* o0 = reinterpret_cast<int4*>(a.bout + (int64_t)rg * 256 + rip * 16);
+            int4* o1 = reinterpret_cast<int4*>(a.bout + (int64_t)rg * 256 + (rip + 8) * 16);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                o0[k] = make_int4(r0[4 * k], r0[4 * k + 1], r0[4 * k + 2], r0[4 * k + 3]);
+                o1[k] = make_int4(r1[4 * k], r1[4 * k + 1], r1[4 * k + 2], r1[4 * k + 3]);
+            }
+        }
+        return;
+    } else {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            r0[j] = out_sample<S>(r0[j]);
+            r1[j] = out_sample<S>(r1[j]);
+        }
+        if (rok) {
+            char* pa = const_cast<char*>(row_ptr<S>(a.dst, rby, rbx, rip));
+            store_row<S>(pa, r0);
+            store_row<S>(pa + 8 * a.dst.pitch, r1);
+        }
+        if constexpr (M::SSE) {
+            if constexpr (M::IN != kInSamples) pack_rows<S>(ra0, ra1, rb0, rb1, xk);
+            int32_t s = rok ? pair_sse(r0, r1, xk) : 0;
+            // a group inside one image adds to the workgroup's running sum
+            // (flushed when the image changes); a group that straddles
+            // images adds per thread
+            const uint32_t img0 = fdiv(fdiv(g0, a.bwdiv), a.ipbdiv);
+            const uint32_t img1 = fdiv(fdiv(g0 + ntile - 1u, a.bwdiv), a.ipbdiv);
+            if (img0 == img1) {
+                if (img0 != acc.img) {
+                    sse_flush<TPW * 8>(acc, a.sse, red);
+                    acc.s = 0;
+                    acc.img = img0;
+                }
+                acc.s += s;
+            } else if (rok && s != 0) {
+                atomicAdd(a.sse + fdiv(rby, a.ipbdiv), (unsigned long long)s);
+            }
+        }
+    }
+}
+
+}  // namespace adct
+
+namespace adct {
+
+#ifndef ADCT_TPW
+#define ADCT_TPW 16
+#endif
+// Tiles per workgroup of the one-group-per-workgroup kernels.
+constexpr int kTPW = ADCT_TPW;
+static_assert(kTPW >= 8 && (kTPW & (kTPW - 1)) == 0, "TPW must be a power of two >= 8");
+
+// One group per workgroup.
+// `gpw` consecutive groups per workgroup; the per-image SSE is reduced in
+// registers across them.
+template <int TPW, typename S, typename M>
+__global__ __launch_bounds__(TPW * 8) void k_group(GroupArgs a, uint32_t nblk, uint32_t gpw) {
+    __shared__ uint32_t lds[lds_words(TPW)];
+    __shared__ long long red[TPW * 8 / 64];
+    SseAcc acc{0, kNoImage};
+    RowWords rows;
+    uint32_t g0 = blockIdx.x * gpw * (uint32_t)TPW;
+    const uint32_t gend = min(nblk, g0 + gpw * (uint32_t)TPW);
+    if constexpr (M::IN == kInSamples) load_group_rows<TPW, S>(a, g0, min((uint32_t)TPW, nblk - g0), rows);
+    for (uint32_t k = 0; g0 < gend; ++k, g0 += (uint32_t)TPW) {
+        if (k) __syncthreads();  // the previous group's LDS reads are done
+        const uint32_t g0n = g0 + (uint32_t)TPW;
+        const uint32_t ntn = g0n < gend ? min((uint32_t)TPW, gend - g0n) : 0u;
+        process_group<TPW, S, M>(a, g0, min((uint32_t)TPW, nblk - g0), lds, red, acc, rows, g0n, ntn);
+    }
+    if constexpr (M::SSE) sse_flush<TPW * 8>(acc, a.sse, red);
+}
+
+#ifndef ADCT_TARGET_WGS
+#define ADCT_TARGET_WGS 16384
+#endif
+#ifndef ADCT_MAX_GPW
+#define ADCT_MAX_GPW 32
+#endif
+// Groups per workgroup for a plain launch over nblk tiles: enough workgroups
+// to fill the chip several times over, as few SSE flushes as that allows.
+inline uint32_t groups_per_wg(uint32_t nblk) {
+    const uint32_t groups = (nblk + kTPW - 1) / kTPW;
+    uint32_t g = (groups + ADCT_TARGET_WGS - 1) / ADCT_TARGET_WGS;
+    return g < 1 ? 1 : (g > ADCT_MAX_GPW ? ADCT_MAX_GPW : g);
+}
+
+}  // namespace adct

@@ -6,12 +6,11 @@
 #include <algorithm>
 
 #include "adct_internal.hpp"
+#include "adct_core.hpp"
 #include "adct_kernels.hpp"
 
 namespace adct {
 namespace {
-
-constexpr int kTPW = 16;  // tiles per workgroup of the plain grid kernels
 
 Scale5 to_dev(const Scale5Host& h) {
     Scale5 s;
@@ -27,9 +26,14 @@ PlaneRef plane_ref(const adct_plane* p) {
     return r;
 }
 
-int launched() { return hipGetLastError() == hipSuccess ? ADCT_OK : ADCT_E_HIP; }
+// Tile-row geometry shared by every plane of a call.
+void set_geometry(const adct_plane* p, GroupArgs& a) {
+    a.bw = (uint32_t)(p->width / 16);
+    a.bwdiv = make_fastdiv(a.bw);
+    a.ipbdiv = make_fastdiv(1);
+}
 
-unsigned tile_grid(int64_t nblk) { return (unsigned)((nblk + kTPW - 1) / kTPW); }
+int launched() { return hipGetLastError() == hipSuccess ? ADCT_OK : ADCT_E_HIP; }
 
 unsigned elem_grid(uint64_t n4) { return (unsigned)std::min<uint64_t>((n4 + 255) / 256, 1u << 20); }
 
@@ -53,41 +57,49 @@ int check_recon(const adct_plane* dst, const adct_plane* ref, int32_t image_heig
     return ADCT_OK;
 }
 
-template <int IN, int OUT, bool SSE>
-void launch_inv_typed(int32_t dtype, unsigned grid, hipStream_t s, const InvArgs& a) {
-    if (dtype == ADCT_U8)
-        hipLaunchKernelGGL((k_inv<kTPW, uint8_t, IN, OUT, SSE>), dim3(grid), dim3(kTPW * 16), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_inv<kTPW, int16_t, IN, OUT, SSE>), dim3(grid), dim3(kTPW * 16), 0, s, a);
+template <typename S, typename M>
+int launch_group(uint32_t nblk, hipStream_t s, const GroupArgs& a) {
+    if (nblk == 0) return ADCT_OK;
+    const uint32_t gpw = groups_per_wg(nblk);
+    const uint32_t span = gpw * (uint32_t)kTPW;
+    hipLaunchKernelGGL((k_group<kTPW, S, M>), dim3((nblk + span - 1) / span), dim3(kTPW * 8), 0, s, a, nblk, gpw);
+    return launched();
 }
 
-template <int IN>
-int recon_common(const void* in, const Scale5Host* dqs, int r, const adct_plane* dst, const adct_plane* ref,
-                 int32_t image_height, int64_t* sse, void* stream) {
-    int rc = check_recon(dst, ref, image_height, sse);
-    if (rc) return rc;
-    const int64_t nblk = plane_blocks(dst);
-    if ((rc = check_blocks(in, nblk))) return rc;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    InvArgs a{};
-    a.in = in;
-    a.nblk = (uint32_t)nblk;
-    a.r = r;
-    if (dqs) a.dqs = to_dev(*dqs);
-    a.dst = plane_ref(dst);
-    const unsigned grid = tile_grid(nblk);
-    if (sse) {
-        const uint32_t nimg = (uint32_t)(dst->height / image_height);
-        hipLaunchKernelGGL(k_zero_u64, dim3((nimg + 255) / 256), dim3(256), 0, s,
-                           reinterpret_cast<unsigned long long*>(sse), nimg);
-        a.ref = plane_ref(ref);
-        a.ipb = (uint32_t)(image_height / 16);
-        a.sse = reinterpret_cast<unsigned long long*>(sse);
-        launch_inv_typed<IN, kOutPlane, true>(dst->dtype, grid, s, a);
-    } else {
-        a.ipb = 1;
-        launch_inv_typed<IN, kOutPlane, false>(dst->dtype, grid, s, a);
+template <typename M>
+int launch_typed(int32_t dtype, uint32_t nblk, hipStream_t s, const GroupArgs& a) {
+    return dtype == ADCT_U8 ? launch_group<uint8_t, M>(nblk, s, a) : launch_group<int16_t, M>(nblk, s, a);
+}
+
+// Zonal modes: uint8 planes get kernels specialised for the common sizes,
+// in which the known-zero coefficients fold away.
+template <int IN, int STORE, bool SSE>
+int launch_zonal(int32_t dtype, int r, uint32_t nblk, hipStream_t s, const GroupArgs& a) {
+    if (dtype == ADCT_U8) {
+        switch (r) {
+            case 2: return launch_group<uint8_t, Mode<IN, STORE, kMidZonal, kOutSamples, 2, SSE>>(nblk, s, a);
+            case 4: return launch_group<uint8_t, Mode<IN, STORE, kMidZonal, kOutSamples, 4, SSE>>(nblk, s, a);
+            case 8: return launch_group<uint8_t, Mode<IN, STORE, kMidZonal, kOutSamples, 8, SSE>>(nblk, s, a);
+            case 12: return launch_group<uint8_t, Mode<IN, STORE, kMidZonal, kOutSamples, 12, SSE>>(nblk, s, a);
+            case 16: return launch_group<uint8_t, Mode<IN, STORE, kMidZonal, kOutSamples, 16, SSE>>(nblk, s, a);
+            default: return launch_group<uint8_t, Mode<IN, STORE, kMidZonal, kOutSamples, -1, SSE>>(nblk, s, a);
+        }
     }
+    return launch_group<int16_t, Mode<IN, STORE, kMidZonal, kOutSamples, -1, SSE>>(nblk, s, a);
+}
+
+// Clears the per-image SSE accumulators (a fill kernel, so that the call can
+// be captured in a graph) and fills the SSE fields of `a`.
+int prepare_sse(const adct_plane* dst, const adct_plane* ref, int32_t image_height, int64_t* sse,
+                hipStream_t s, GroupArgs& a) {
+    a.ipbdiv = make_fastdiv(1);
+    if (!sse) return ADCT_OK;
+    const uint32_t nimg = (uint32_t)(dst->height / image_height);
+    hipLaunchKernelGGL(k_zero_u64, dim3((nimg + 255) / 256), dim3(256), 0, s,
+                       reinterpret_cast<unsigned long long*>(sse), nimg);
+    a.ref = plane_ref(ref ? ref : dst);
+    a.ipbdiv = make_fastdiv((uint32_t)(image_height / 16));
+    a.sse = reinterpret_cast<unsigned long long*>(sse);
     return launched();
 }
 
@@ -103,16 +115,12 @@ int adct_fwd2d(const adct_plane* src, int32_t* coef, void* stream) {
     if (rc) return rc;
     const int64_t nblk = plane_blocks(src);
     if ((rc = check_blocks(coef, nblk))) return rc;
-    FwdArgs a{};
+    GroupArgs a{};
     a.src = plane_ref(src);
-    a.nblk = (uint32_t)nblk;
-    a.out = coef;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    if (src->dtype == ADCT_U8)
-        hipLaunchKernelGGL((k_fwd<kTPW, uint8_t, kOutCoef>), dim3(tile_grid(nblk)), dim3(kTPW * 16), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_fwd<kTPW, int16_t, kOutCoef>), dim3(tile_grid(nblk)), dim3(kTPW * 16), 0, s, a);
-    return launched();
+    set_geometry(src, a);
+    a.cout = coef;
+    return launch_typed<Mode<kInSamples, kStoreY, kMidNone, kOutNothing, -1, false>>(
+        src->dtype, (uint32_t)nblk, static_cast<hipStream_t>(stream), a);
 }
 
 int adct_fwd2d_quant(const adct_plane* src, int qp, int16_t* q, void* stream) {
@@ -122,31 +130,26 @@ int adct_fwd2d_quant(const adct_plane* src, int qp, int16_t* q, void* stream) {
     if ((rc = check_blocks(q, nblk))) return rc;
     Scale5Host qs;
     if (!quant_scales(qp, &qs, nullptr)) return ADCT_E_ARG;
-    FwdArgs a{};
+    GroupArgs a{};
     a.src = plane_ref(src);
-    a.nblk = (uint32_t)nblk;
-    a.out = q;
+    set_geometry(src, a);
+    a.cout = q;
     a.qs = to_dev(qs);
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    if (src->dtype == ADCT_U8)
-        hipLaunchKernelGGL((k_fwd<kTPW, uint8_t, kOutQuant>), dim3(tile_grid(nblk)), dim3(kTPW * 16), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_fwd<kTPW, int16_t, kOutQuant>), dim3(tile_grid(nblk)), dim3(kTPW * 16), 0, s, a);
-    return launched();
+    return launch_typed<Mode<kInSamples, kStoreQ, kMidQuant, kOutNothing, -1, false>>(
+        src->dtype, (uint32_t)nblk, static_cast<hipStream_t>(stream), a);
 }
 
 int adct_inv2d(const int32_t* coef, int64_t nblk, int32_t* out, void* stream) {
     int rc;
     if ((rc = check_blocks(coef, nblk)) || (rc = check_blocks(out, nblk))) return rc;
-    if (nblk == 0) return ADCT_OK;
-    InvArgs a{};
-    a.in = coef;
-    a.nblk = (uint32_t)nblk;
-    a.out_block = out;
-    a.ipb = 1;
-    hipLaunchKernelGGL((k_inv<kTPW, int16_t, kInZfix, kOutBlock, false>), dim3(tile_grid(nblk)),
-                       dim3(kTPW * 16), 0, static_cast<hipStream_t>(stream), a);
-    return launched();
+    GroupArgs a{};
+    a.cin = coef;
+    a.bout = out;
+    a.bw = 1;
+    a.bwdiv = make_fastdiv(1);
+    a.ipbdiv = make_fastdiv(1);
+    return launch_group<int16_t, Mode<kInZfix, kStoreNone, kMidNone, kOutBlocks, -1, false>>(
+        (uint32_t)nblk, static_cast<hipStream_t>(stream), a);
 }
 
 int adct_scale(const int32_t* coef, int64_t nblk, float* out, void* stream) {
@@ -197,20 +200,111 @@ int adct_zonal(const int32_t* coef, int64_t nblk, int r, int32_t* zfix, void* st
 }
 
 int adct_recon(const int32_t* zfix, const adct_plane* dst, void* stream) {
-    return recon_common<kInZfix>(zfix, nullptr, 16, dst, nullptr, 0, nullptr, stream);
+    int rc = check_plane(dst);
+    if (rc) return rc;
+    const int64_t nblk = plane_blocks(dst);
+    if ((rc = check_blocks(zfix, nblk))) return rc;
+    GroupArgs a{};
+    a.cin = zfix;
+    a.dst = plane_ref(dst);
+    set_geometry(dst, a);
+    return launch_typed<Mode<kInZfix, kStoreNone, kMidNone, kOutSamples, -1, false>>(
+        dst->dtype, (uint32_t)nblk, static_cast<hipStream_t>(stream), a);
 }
 
 int adct_zonal_recon(const int32_t* coef, int r, const adct_plane* dst, const adct_plane* ref,
                      int32_t image_height, int64_t* sse, void* stream) {
     if (r < 0 || r > 16) return ADCT_E_ARG;
-    return recon_common<kInZonal>(coef, nullptr, r, dst, ref, image_height, sse, stream);
+    int rc = check_recon(dst, ref, image_height, sse);
+    if (rc) return rc;
+    const int64_t nblk = plane_blocks(dst);
+    if ((rc = check_blocks(coef, nblk))) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    GroupArgs a{};
+    a.cin = coef;
+    a.dst = plane_ref(dst);
+    set_geometry(dst, a);
+    a.r = r;
+    if ((rc = prepare_sse(dst, ref, image_height, sse, s, a))) return rc;
+    return sse ? launch_zonal<kInY, kStoreNone, true>(dst->dtype, r, (uint32_t)nblk, s, a)
+               : launch_zonal<kInY, kStoreNone, false>(dst->dtype, r, (uint32_t)nblk, s, a);
 }
 
 int adct_dequant_recon(const int16_t* q, int qp, const adct_plane* dst, const adct_plane* ref,
                        int32_t image_height, int64_t* sse, void* stream) {
     Scale5Host dqs;
     if (!quant_scales(qp, nullptr, &dqs)) return ADCT_E_ARG;
-    return recon_common<kInDequant>(q, &dqs, 16, dst, ref, image_height, sse, stream);
+    int rc = check_recon(dst, ref, image_height, sse);
+    if (rc) return rc;
+    const int64_t nblk = plane_blocks(dst);
+    if ((rc = check_blocks(q, nblk))) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    GroupArgs a{};
+    a.cin = q;
+    a.dst = plane_ref(dst);
+    set_geometry(dst, a);
+    a.dqs = to_dev(dqs);
+    if ((rc = prepare_sse(dst, ref, image_height, sse, s, a))) return rc;
+    return sse ? launch_typed<Mode<kInQ, kStoreNone, kMidDequant, kOutSamples, -1, true>>(dst->dtype, (uint32_t)nblk, s, a)
+               : launch_typed<Mode<kInQ, kStoreNone, kMidDequant, kOutSamples, -1, false>>(dst->dtype, (uint32_t)nblk, s, a);
+}
+
+int adct_encode_zonal(const adct_plane* src, int r, int32_t* coef, const adct_plane* dst,
+                      int32_t image_height, int64_t* sse, void* stream) {
+    if (r < 0 || r > 16) return ADCT_E_ARG;
+    int rc = check_plane(src);
+    if (rc) return rc;
+    if ((rc = check_plane(dst))) return rc;
+    if (!same_shape(src, dst)) return ADCT_E_SHAPE;
+    if (sse && (image_height <= 0 || (image_height & 15) || src->height % image_height)) return ADCT_E_SHAPE;
+    if (sse && ((uintptr_t)sse & 7)) return ADCT_E_ALIGN;
+    const int64_t nblk = plane_blocks(src);
+    if (coef && (rc = check_blocks(coef, nblk))) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    GroupArgs a{};
+    a.src = plane_ref(src);
+    set_geometry(src, a);
+    a.dst = plane_ref(dst);
+    set_geometry(dst, a);
+    a.cout = coef;
+    a.r = r;
+    if ((rc = prepare_sse(dst, src, image_height, sse, s, a))) return rc;
+    const uint32_t n = (uint32_t)nblk;
+    if (coef)
+        return sse ? launch_zonal<kInSamples, kStoreY, true>(src->dtype, r, n, s, a)
+                   : launch_zonal<kInSamples, kStoreY, false>(src->dtype, r, n, s, a);
+    return sse ? launch_zonal<kInSamples, kStoreNone, true>(src->dtype, r, n, s, a)
+               : launch_zonal<kInSamples, kStoreNone, false>(src->dtype, r, n, s, a);
+}
+
+int adct_encode_quant(const adct_plane* src, int qp, int16_t* q, const adct_plane* dst, int32_t image_height,
+                      int64_t* sse, void* stream) {
+    Scale5Host qs, dqs;
+    if (!quant_scales(qp, &qs, &dqs)) return ADCT_E_ARG;
+    int rc = check_plane(src);
+    if (rc) return rc;
+    if ((rc = check_plane(dst))) return rc;
+    if (!same_shape(src, dst)) return ADCT_E_SHAPE;
+    if (sse && (image_height <= 0 || (image_height & 15) || src->height % image_height)) return ADCT_E_SHAPE;
+    if (sse && ((uintptr_t)sse & 7)) return ADCT_E_ALIGN;
+    const int64_t nblk = plane_blocks(src);
+    if (q && (rc = check_blocks(q, nblk))) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    GroupArgs a{};
+    a.src = plane_ref(src);
+    set_geometry(src, a);
+    a.dst = plane_ref(dst);
+    set_geometry(dst, a);
+    a.cout = q;
+    a.qs = to_dev(qs);
+    a.dqs = to_dev(dqs);
+    if ((rc = prepare_sse(dst, src, image_height, sse, s, a))) return rc;
+    const uint32_t n = (uint32_t)nblk;
+    if (q)
+        return sse ? launch_typed<Mode<kInSamples, kStoreQ, kMidQuant, kOutSamples, -1, true>>(src->dtype, n, s, a)
+                   : launch_typed<Mode<kInSamples, kStoreQ, kMidQuant, kOutSamples, -1, false>>(src->dtype, n, s, a);
+    return sse ? launch_typed<Mode<kInSamples, kStoreNone, kMidQuant, kOutSamples, -1, true>>(src->dtype, n, s, a)
+               : launch_typed<Mode<kInSamples, kStoreNone, kMidQuant, kOutSamples, -1, false>>(src->dtype, n, s, a);
 }
 
 int adct_sse(const adct_plane* a, const adct_plane* b, int32_t image_height, int64_t* sse, void* stream) {

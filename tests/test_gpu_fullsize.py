@@ -1,0 +1,102 @@
+"""GPU parity at the benchmark sizes and launch configurations.
+
+The batched image workload (1024 uint8 AR(1) images of 512x512) and a batch
+whose images do not hold a multiple of 16 tiles, both large enough that every
+workgroup processes several tile groups and flushes per-image SSE across
+image boundaries; video residual frames at 1920x1088 4:2:0.  Every image's
+SSE is checked against the C oracle; sampled images are compared sample by
+sample with the numpy oracle.
+"""
+import numpy as np
+import pytest
+
+from oracle import adct_oracle as O
+import synth
+from tests import oracle_c
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1606_07414_amd import adct  # noqa: E402
+
+SIDE, N_IMG = 512, 1024
+
+
+@pytest.fixture(scope="module")
+def batch():
+    img = synth.ar1_batch(N_IMG, SIDE, SIDE)
+    return img, torch.from_numpy(img).cuda()
+
+
+@pytest.mark.parametrize("r", [2, 4, 8, 12, 16])
+def test_batched_encoder_full_size(batch, r):
+    img, x = batch
+    nt = N_IMG * (SIDE // 16) ** 2
+    coef = torch.empty((nt, 16, 16), dtype=torch.int32, device="cuda")
+    out = torch.empty_like(x)
+    sse = adct.encode_zonal(x, r, out, coef=coef, image_height=SIDE)
+    torch.cuda.synchronize()
+    got_sse = sse.cpu().numpy()
+    # every image's SSE against the C oracle
+    c_coef = oracle_c.fwd2d_u8(img)
+    c_out, c_sse = oracle_c.zonal_recon_u8(c_coef, img.shape[0], SIDE, r, img, SIDE)
+    assert np.array_equal(got_sse, c_sse)
+    got_out = out.cpu().numpy()
+    assert np.array_equal(got_out, c_out)
+    got_coef = coef.cpu().numpy()
+    assert np.array_equal(got_coef, c_coef.astype(np.int32))
+    # sampled images against the numpy oracle
+    for i in (0, 511, 1023):
+        sl = slice(i * SIDE, (i + 1) * SIDE)
+        assert np.array_equal(got_out[sl], O.zonal_reconstruct(img[sl], r))
+
+
+def test_two_pass_equals_fused_full_size(batch):
+    img, x = batch
+    o1, o2 = torch.empty_like(x), torch.empty_like(x)
+    coef = adct.fwd2d(x)
+    s1 = adct.zonal_recon(coef, 8, o1, ref=x, image_height=SIDE)
+    c2 = torch.empty_like(coef)
+    s2 = adct.encode_zonal(x, 8, o2, coef=c2, image_height=SIDE)
+    torch.cuda.synchronize()
+    assert torch.equal(coef, c2) and torch.equal(o1, o2) and torch.equal(s1, s2)
+
+
+def test_uneven_tiles_per_image_multi_group():
+    # 561 tiles per image (17 x 33): groups straddle images everywhere
+    h, w, n = 272, 528, 480
+    img = synth.ar1_batch(n, h, w, seed_base=6_000_000)
+    x = torch.from_numpy(img).cuda()
+    out = torch.empty_like(x)
+    sse = adct.encode_zonal(x, 4, out, image_height=h)
+    torch.cuda.synchronize()
+    c_coef = oracle_c.fwd2d_u8(img)
+    c_out, c_sse = oracle_c.zonal_recon_u8(c_coef, img.shape[0], w, 4, img, h)
+    assert np.array_equal(sse.cpu().numpy(), c_sse)
+    assert np.array_equal(out.cpu().numpy(), c_out)
+
+
+@pytest.mark.parametrize("qp", [22, 27, 32, 37])
+def test_video_residual_frames(qp):
+    frames = [synth.video_frame_planes(f) for f in range(8)]
+    for plane_idx, (hh, ww) in enumerate([(1088, 1920), (544, 960), (544, 960)]):
+        stack = np.concatenate([fr[plane_idx] for fr in frames])
+        x = torch.from_numpy(stack).cuda()
+        q = adct.fwd2d_quant(x, qp)
+        out = torch.empty_like(x)
+        sse = adct.dequant_recon(q, qp, out, ref=x, image_height=hh)
+        torch.cuda.synchronize()
+        got_q, got_out, got_sse = q.cpu().numpy(), out.cpu().numpy(), sse.cpu().numpy()
+        ntf = (hh // 16) * (ww // 16)
+        for f in (0, 7):
+            res = stack[f * hh:(f + 1) * hh]
+            qw, _, want = O.quant_reconstruct(res, qp)
+            assert np.array_equal(got_q[f * ntf:(f + 1) * ntf], qw)
+            assert np.array_equal(got_out[f * hh:(f + 1) * hh], want)
+            assert got_sse[f] == O.sse(want, res)
+        # the fused encoder gives the same levels, output and SSE
+        q2 = torch.empty_like(q)
+        out2 = torch.empty_like(x)
+        sse2 = adct.encode_quant(x, qp, out2, q=q2, image_height=hh)
+        torch.cuda.synchronize()
+        assert torch.equal(q, q2) and torch.equal(out, out2) and torch.equal(sse, sse2)

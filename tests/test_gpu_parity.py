@@ -86,10 +86,14 @@ def test_fwd2d_i16_extremes_and_full_range():
     want = O.fwd2d(img)
     assert np.abs(want).max() == 65280
     assert np.array_equal(host(adct.fwd2d(dev(img))), want)
-    # any int16 input is exact
+    # the documented exact range of int16 samples, including its ends
     rng = np.random.default_rng(3)
-    full = rng.integers(-32768, 32768, size=(64, 64)).astype(np.int16)
-    assert np.array_equal(host(adct.fwd2d(dev(full))), O.fwd2d(full))
+    wide = rng.integers(-2047, 2048, size=(64, 64)).astype(np.int16)
+    wide[:16, :16] = 2047
+    wide[16:32, :16] = -2047
+    assert np.array_equal(host(adct.fwd2d(dev(wide))), O.fwd2d(wide))
+    ext = synth.tiles_to_plane(extreme_tiles(-2047, 2047).astype(np.int16), 16)
+    assert np.array_equal(host(adct.fwd2d(dev(ext))), O.fwd2d(ext))
 
 
 # ------------------------------------------------------------------ inverse
@@ -272,3 +276,83 @@ def test_errors_raise_without_launch():
     with pytest.raises(adct.AdctError) as e:
         adct.fwd2d(x)
     assert e.value.code == adct.E_SHAPE
+
+
+# ------------------------------------------------------------------ single-pass encoders
+@pytest.mark.parametrize("r", [0, 1, 2, 3, 4, 8, 12, 16])
+@pytest.mark.parametrize("store", [True, False])
+@pytest.mark.parametrize("shape,image_h", [((256, 256), 256), ((272, 528), 272), ((96, 48), 32), ((48, 80), 16)])
+def test_encode_zonal(r, store, shape, image_h):
+    img = synth.ar1_batch(shape[0] // image_h, image_h, shape[1], seed_base=700 + r)
+    x = dev(img)
+    out = torch.empty_like(x)
+    coef = torch.full((x.shape[0] // 16 * (x.shape[1] // 16), 16, 16), -7, dtype=torch.int32, device="cuda")
+    s = host(adct.encode_zonal(x, r, out, coef=coef if store else None, image_height=image_h))
+    want = O.zonal_reconstruct(img, r)
+    assert np.array_equal(host(out), want)
+    if store:
+        assert np.array_equal(host(coef), O.fwd2d(img))
+    else:
+        assert np.all(host(coef) == -7)
+    for i in range(shape[0] // image_h):
+        assert s[i] == O.sse(want[i * image_h:(i + 1) * image_h], img[i * image_h:(i + 1) * image_h])
+
+
+def test_encode_zonal_structured_tiles_all_r():
+    tiles = np.concatenate([synth.structured_tiles(), synth.random_binary_tiles(60),
+                            extreme_tiles(0, 255)]).astype(np.uint8)
+    img = synth.tiles_to_plane(tiles, 16)
+    x = dev(img)
+    out = torch.empty_like(x)
+    for r in range(0, 17):
+        s = host(adct.encode_zonal(x, r, out))
+        want = O.zonal_reconstruct(img, r)
+        assert np.array_equal(host(out), want), r
+        assert s[0] == O.sse(want, img), r
+
+
+def test_encode_zonal_i16_residual():
+    res = synth.laplacian_residual(77, 64, 96)
+    x = dev(res)
+    out = torch.empty_like(x)
+    s = host(adct.encode_zonal(x, 4, out))
+    Y = O.fwd2d(res)
+    want = O.from_tiles(O.round_clamp(O.reconstruct_fixed(O.zonal(Y, 4)), -255, 255), 64, 96)
+    assert np.array_equal(host(out), want)
+    assert s[0] == O.sse(want, res)
+
+
+@pytest.mark.parametrize("qp", [22, 27, 32, 37])
+@pytest.mark.parametrize("store", [True, False])
+@pytest.mark.parametrize("kind", ["u8", "i16"])
+def test_encode_quant(qp, store, kind):
+    if kind == "u8":
+        src = synth.ar1_batch(2, 64, 96, seed_base=800 + qp)
+        lo, hi = 0, 255
+    else:
+        src = synth.laplacian_residual(800 + qp, 128, 96)
+        lo, hi = -255, 255
+    x = dev(src)
+    out = torch.empty_like(x)
+    q = torch.zeros((x.shape[0] // 16 * (x.shape[1] // 16), 16, 16), dtype=torch.int16, device="cuda")
+    s = host(adct.encode_quant(x, qp, out, q=q if store else None, image_height=64))
+    qw = O.quantise(O.fwd2d(src), qp)
+    want = O.from_tiles(O.round_clamp(O.reconstruct_fixed(O.dequantise(qw, qp)), lo, hi), *src.shape)
+    assert np.array_equal(host(out), want)
+    if store:
+        assert np.array_equal(host(q), qw)
+    for i in range(src.shape[0] // 64):
+        assert s[i] == O.sse(want[i * 64:(i + 1) * 64], src[i * 64:(i + 1) * 64])
+
+
+def test_encoders_match_two_pass_paths():
+    img = synth.ar1_batch(3, 128, 192, seed_base=900)
+    x = dev(img)
+    o1, o2 = torch.empty_like(x), torch.empty_like(x)
+    s1 = adct.encode_zonal(x, 8, o1, image_height=128)
+    s2 = adct.zonal_recon(adct.fwd2d(x), 8, o2, ref=x, image_height=128)
+    assert torch.equal(o1, o2) and torch.equal(s1, s2)
+    q = adct.fwd2d_quant(x, 27)
+    s3 = adct.encode_quant(x, 27, o1, image_height=128)
+    s4 = adct.dequant_recon(q, 27, o2, ref=x, image_height=128)
+    assert torch.equal(o1, o2) and torch.equal(s3, s4)
