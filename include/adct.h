@@ -195,6 +195,78 @@ int adct_encode_zonal(const adct_plane* src, int r, int32_t* coef, const adct_pl
 int adct_encode_quant(const adct_plane* src, int qp, int16_t* q, const adct_plane* dst,
                       int32_t image_height, int64_t* sse, void* stream);
 
+/* ---- uneven batches: one persistent launch over a device work queue -- */
+/* Many images of different sizes coded by ONE launch: the host cuts every
+ * image into items (runs of consecutive tiles that never span two images),
+ * and persistent workgroups claim items from a device queue with one atomic
+ * per claim until the queue is empty.  The reset of the queue and the launch
+ * are captured once into a hipGraph that adct_batch_submit replays.
+ * Per image the result is bit-identical to adct_encode_zonal /
+ * adct_encode_quant on that image alone. */
+
+typedef struct adct_job {
+    adct_plane src;   /* input image, U8 or I16 (one type per batch)            */
+    adct_plane dst;   /* reconstruction, same shape and type as src             */
+    void* coef;       /* ADCT_OP_ZONAL: int32 coefficients; ADCT_OP_QUANT: int16
+                         levels; block-major [nblk][16][16]; NULL: not stored    */
+    int64_t* sse;     /* device int64: exact SSE of dst against src, or NULL    */
+} adct_job;
+
+typedef struct adct_tune {
+    int32_t tiles_per_group;  /* 8, 16 or 32 tiles transformed together by one
+                                 workgroup of 8 threads per tile (1, 2 or 4
+                                 wavefronts)                                   */
+    int32_t groups_per_item;  /* tile groups per queue item, 1..64              */
+    int32_t wgs_per_cu;       /* persistent workgroups per compute unit, 1..16  */
+    int32_t reserved;
+} adct_tune;
+
+#define ADCT_OP_ZONAL 1  /* param = r in [0, 16]  (adct_encode_zonal per image) */
+#define ADCT_OP_QUANT 2  /* param = qp in [0, 63] (adct_encode_quant per image) */
+
+typedef struct adct_batch adct_batch;
+
+/* The tuning used when none is given (host only). */
+int adct_default_tune(adct_tune* out);
+
+/* Host-side work-queue construction (no GPU needed): job j holds
+ * tiles_per_job[j] tiles; items are written as triples (job, first tile,
+ * tile count), each a run of at most tiles_per_group * groups_per_item
+ * consecutive tiles of one job, in job order.  `items` holds room for
+ * `capacity` triples; *n_items receives the count (ADCT_E_TOO_LARGE, with
+ * *n_items set, when capacity is short; items may be NULL to count only). */
+int adct_work_queue(const int64_t* tiles_per_job, int32_t njobs, int32_t tiles_per_group,
+                    int32_t groups_per_item, uint32_t* items, int64_t capacity, int64_t* n_items);
+
+/* Validates the jobs, builds the queue, uploads it and the job table to
+ * library-owned device memory, and captures the graph (on the current
+ * device).  `tune` NULL = adct_default_tune.  The job array is copied; the
+ * buffers it points to stay owned by the caller and must outlive the batch.
+ * Synchronous; ADCT_E_NOMEM / ADCT_E_HIP on allocation or runtime failure. */
+int adct_batch_create(adct_batch** out, const adct_job* jobs, int32_t njobs, int32_t op, int32_t param,
+                      const adct_tune* tune);
+
+/* Replays the batch on `stream` (asynchronous).  Submissions of one batch on
+ * different streams must not overlap: they share the queue. */
+int adct_batch_submit(adct_batch* b, void* stream);
+
+/* Tiles, queue items and the tuning of a batch (host). */
+int adct_batch_info(const adct_batch* b, int64_t* tiles, int64_t* items, adct_tune* tune);
+
+/* Releases the batch (synchronises its last submission first). */
+int adct_batch_destroy(adct_batch* b);
+
+/* Chooses a tuning for (op, param, these jobs) by timing every candidate
+ * (tiles_per_group x groups_per_item x wgs_per_cu) `reps` times on the jobs
+ * themselves -- their dst, coef and sse buffers are overwritten -- and keeps
+ * the fastest.  When `cache_path` is non-NULL, a cached entry for the same
+ * device architecture, compute-unit count, op, param and sample type is
+ * returned without timing, and a new result is appended to the file (one
+ * JSON object per line).  *ms (may be NULL) receives the chosen candidate's
+ * median time, or -1 when it came from the cache.  Synchronous. */
+int adct_autotune(int32_t op, int32_t param, const adct_job* jobs, int32_t njobs, const char* cache_path,
+                  int32_t reps, adct_tune* out, double* ms);
+
 #ifdef __cplusplus
 }
 #endif

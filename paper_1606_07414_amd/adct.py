@@ -32,6 +32,21 @@ class Plane(ctypes.Structure):
                 ("width", ctypes.c_int32), ("reserved", ctypes.c_int32), ("pitch_bytes", ctypes.c_int64)]
 
 
+class Job(ctypes.Structure):
+    _fields_ = [("src", Plane), ("dst", Plane), ("coef", ctypes.c_void_p), ("sse", ctypes.c_void_p)]
+
+
+class Tune(ctypes.Structure):
+    _fields_ = [("tiles_per_group", ctypes.c_int32), ("groups_per_item", ctypes.c_int32),
+                ("wgs_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {"tiles_per_group": self.tiles_per_group, "groups_per_item": self.groups_per_item,
+                "wgs_per_cu": self.wgs_per_cu}
+
+
+OP_ZONAL, OP_QUANT = 1, 2
+
 _P = ctypes.c_void_p
 _PP = ctypes.POINTER(Plane)
 _I32, _I64, _D = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
@@ -56,6 +71,15 @@ _SIGNATURES = {
     "adct_dequant_recon": (ctypes.c_int, [_P, ctypes.c_int, _PP, _PP, _I32, _P, _P]),
     "adct_encode_zonal": (ctypes.c_int, [_PP, ctypes.c_int, _P, _PP, _I32, _P, _P]),
     "adct_encode_quant": (ctypes.c_int, [_PP, ctypes.c_int, _P, _PP, _I32, _P, _P]),
+    "adct_default_tune": (ctypes.c_int, [ctypes.POINTER(Tune)]),
+    "adct_work_queue": (ctypes.c_int, [_P, _I32, _I32, _I32, _P, _I64, ctypes.POINTER(_I64)]),
+    "adct_batch_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.POINTER(Job), _I32, _I32, _I32,
+                                         ctypes.POINTER(Tune)]),
+    "adct_batch_submit": (ctypes.c_int, [_P, _P]),
+    "adct_batch_info": (ctypes.c_int, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(Tune)]),
+    "adct_batch_destroy": (ctypes.c_int, [_P]),
+    "adct_autotune": (ctypes.c_int, [_I32, _I32, ctypes.POINTER(Job), _I32, ctypes.c_char_p, _I32,
+                                     ctypes.POINTER(Tune), ctypes.POINTER(_D)]),
 }
 
 _LIB = None
@@ -302,3 +326,80 @@ def sse(a, b, image_height=None, out=None, stream=None):
     _check(_lib().adct_sse(ctypes.byref(pa), ctypes.byref(pb), image_height, out.data_ptr(), _stream(stream)),
            "sse")
     return out
+
+
+# ---------------------------------------------------------------- uneven batches
+def default_tune() -> Tune:
+    t = Tune()
+    _check(_lib().adct_default_tune(ctypes.byref(t)), "default_tune")
+    return t
+
+
+def make_tune(tiles_per_group: int, groups_per_item: int, wgs_per_cu: int) -> Tune:
+    return Tune(tiles_per_group, groups_per_item, wgs_per_cu, 0)
+
+
+def work_queue(tiles_per_job, tiles_per_group: int, groups_per_item: int) -> np.ndarray:
+    """Items (job, first tile, tile count) as built by the library, shape (n, 3)."""
+    t = np.ascontiguousarray(np.asarray(tiles_per_job, dtype=np.int64).reshape(-1))
+    n = _I64(0)
+    _check(_lib().adct_work_queue(t.ctypes.data, t.shape[0], tiles_per_group, groups_per_item, None, 0,
+                                  ctypes.byref(n)), "work_queue")
+    items = np.empty((max(n.value, 1), 3), dtype=np.uint32)
+    _check(_lib().adct_work_queue(t.ctypes.data, t.shape[0], tiles_per_group, groups_per_item, items.ctypes.data,
+                                  n.value, ctypes.byref(n)), "work_queue")
+    return items[:n.value]
+
+
+def make_jobs(srcs, dsts, coefs=None, sses=None):
+    """A ctypes array of adct_job from lists of device tensors (coef/sse entries may be None)."""
+    n = len(srcs)
+    arr = (Job * n)()
+    for i in range(n):
+        c = coefs[i] if coefs is not None else None
+        e = sses[i] if sses is not None else None
+        arr[i] = Job(plane(srcs[i]), plane(dsts[i]), c.data_ptr() if c is not None else None,
+                     e.data_ptr() if e is not None else None)
+    return arr
+
+
+class Batch:
+    """One persistent, graph-captured launch over uneven images.  Keeps the
+    tensors it was built from alive for its lifetime."""
+
+    def __init__(self, srcs, dsts, op: int, param: int, coefs=None, sses=None, tune: Tune | None = None):
+        self._keep = (list(srcs), list(dsts), coefs, sses)
+        jobs = make_jobs(srcs, dsts, coefs, sses)
+        h = _P()
+        _check(_lib().adct_batch_create(ctypes.byref(h), jobs, len(jobs), op, param,
+                                        ctypes.byref(tune) if tune is not None else None), "batch_create")
+        self._h = h
+
+    def submit(self, stream=None):
+        _check(_lib().adct_batch_submit(self._h, _stream(stream)), "batch_submit")
+
+    def info(self):
+        tiles, items, t = _I64(0), _I64(0), Tune()
+        _check(_lib().adct_batch_info(self._h, ctypes.byref(tiles), ctypes.byref(items), ctypes.byref(t)),
+               "batch_info")
+        return {"tiles": tiles.value, "items": items.value, "tune": t.as_dict()}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(_lib().adct_batch_destroy(self._h), "batch_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(srcs, dsts, op: int, param: int, coefs=None, sses=None, cache_path=None, reps: int = 3):
+    """(Tune, ms) -- ms is -1.0 when the result came from the cache."""
+    jobs = make_jobs(srcs, dsts, coefs, sses)
+    t, ms = Tune(), _D(0.0)
+    _check(_lib().adct_autotune(op, param, jobs, len(jobs), cache_path.encode() if cache_path else None, reps,
+                                ctypes.byref(t), ctypes.byref(ms)), "autotune")
+    return t, ms.value

@@ -467,20 +467,25 @@ __device__ __forceinline__ void process_group(const GroupArgs& a, uint32_t g0, u
     }
 
     // ---------------- coefficient domain ----------------------------------------
+    // (a.cout and a.sse are uniform: a null pointer skips that output)
     if constexpr (M::STORE == kStoreY) {
-        __syncthreads();
-        lds_put_columns(lds, clt, cp, ya, yb);
-        __syncthreads();
-        lds_blocks_to_global<TPW>(lds, tid, ntile, static_cast<int32_t*>(a.cout) + (int64_t)g0 * 256);
+        if (a.cout) {
+            __syncthreads();
+            lds_put_columns(lds, clt, cp, ya, yb);
+            __syncthreads();
+            lds_blocks_to_global<TPW>(lds, tid, ntile, static_cast<int32_t*>(a.cout) + (int64_t)g0 * 256);
+        }
     }
     if constexpr (M::MID == kMidQuant) {
         int32_t qa[16], qb[16];
         quant_cols(a.qs, cp, ya, yb, qa, qb);
         if constexpr (M::STORE == kStoreQ) {
-            __syncthreads();
-            lds_put_q_columns(lds, clt, cp, qa, qb);
-            __syncthreads();
-            lds_q_to_global<TPW>(lds, tid, ntile, static_cast<int16_t*>(a.cout) + (int64_t)g0 * 256);
+            if (a.cout) {
+                __syncthreads();
+                lds_put_q_columns(lds, clt, cp, qa, qb);
+                __syncthreads();
+                lds_q_to_global<TPW>(lds, tid, ntile, static_cast<int16_t*>(a.cout) + (int64_t)g0 * 256);
+            }
         }
         if constexpr (M::OUT != kOutNothing) {
 #pragma unroll
@@ -541,6 +546,7 @@ __device__ __forceinline__ void process_group(const GroupArgs& a, uint32_t g0, u
             store_row<S>(pa + 8 * a.dst.pitch, r1);
         }
         if constexpr (M::SSE) {
+          if (a.sse) {
             if constexpr (M::IN != kInSamples) pack_rows<S>(ra0, ra1, rb0, rb1, xk);
             int32_t s = rok ? pair_sse(r0, r1, xk) : 0;
             // a group inside one image adds to the workgroup's running sum
@@ -558,6 +564,7 @@ __device__ __forceinline__ void process_group(const GroupArgs& a, uint32_t g0, u
             } else if (rok && s != 0) {
                 atomicAdd(a.sse + fdiv(rby, a.ipbdiv), (unsigned long long)s);
             }
+          }
         }
     }
 }
@@ -591,7 +598,9 @@ __global__ __launch_bounds__(TPW * 8) void k_group(GroupArgs a, uint32_t nblk, u
         const uint32_t ntn = g0n < gend ? min((uint32_t)TPW, gend - g0n) : 0u;
         process_group<TPW, S, M>(a, g0, min((uint32_t)TPW, nblk - g0), lds, red, acc, rows, g0n, ntn);
     }
-    if constexpr (M::SSE) sse_flush<TPW * 8>(acc, a.sse, red);
+    if constexpr (M::SSE) {
+        if (a.sse) sse_flush<TPW * 8>(acc, a.sse, red);
+    }
 }
 
 #ifndef ADCT_TARGET_WGS

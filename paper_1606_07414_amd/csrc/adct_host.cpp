@@ -75,7 +75,7 @@ const char* adct_strerror(int code) {
         case ADCT_E_DTYPE: return "unsupported sample type";
         case ADCT_E_HIP: return "HIP runtime error";
         case ADCT_E_NOMEM: return "out of memory";
-        case ADCT_E_TOO_LARGE: return "request larger than the memory pool";
+        case ADCT_E_TOO_LARGE: return "request larger than the available capacity";
         case ADCT_E_STOPPED: return "stopped";
         case ADCT_E_TIMEOUT: return "timed out";
         case ADCT_E_NOTFOUND: return "not found";
@@ -116,6 +116,38 @@ int adct_psnr(const int64_t* sse, int32_t n, double pixels_per_image, double pea
         out[i] = sse[i] == 0 ? INFINITY : 10.0 * log10(peak * peak * pixels_per_image / (double)sse[i]);
     }
     return ADCT_OK;
+}
+
+int adct_default_tune(adct_tune* out) {
+    if (!out) return ADCT_E_ARG;
+    out->tiles_per_group = 16;
+    out->groups_per_item = 4;
+    out->wgs_per_cu = 8;
+    out->reserved = 0;
+    return ADCT_OK;
+}
+
+int adct_work_queue(const int64_t* tiles_per_job, int32_t njobs, int32_t tiles_per_group, int32_t groups_per_item,
+                    uint32_t* items, int64_t capacity, int64_t* n_items) {
+    if (!tiles_per_job || njobs < 0 || !n_items || capacity < 0) return ADCT_E_ARG;
+    if (tiles_per_group <= 0 || groups_per_item <= 0) return ADCT_E_ARG;
+    const int64_t span = (int64_t)tiles_per_group * groups_per_item;
+    int64_t n = 0;
+    for (int32_t j = 0; j < njobs; ++j) {
+        const int64_t t = tiles_per_job[j];
+        if (t < 0 || t > (int64_t)INT32_MAX) return ADCT_E_ARG;
+        for (int64_t first = 0; first < t; first += span) {
+            if (items && n < capacity) {
+                items[3 * n + 0] = (uint32_t)j;
+                items[3 * n + 1] = (uint32_t)first;
+                items[3 * n + 2] = (uint32_t)(t - first < span ? t - first : span);
+            }
+            ++n;
+        }
+    }
+    *n_items = n;
+    if (n > (int64_t)UINT32_MAX) return ADCT_E_TOO_LARGE;
+    return (items && n > capacity) ? ADCT_E_TOO_LARGE : ADCT_OK;
 }
 
 // Host execution of the kernels' 1D butterflies (the same code the GPU

@@ -154,3 +154,61 @@ def test_recon_reference_rules():
     assert lib.adct_zonal_recon(FAKE, 4, ctypes.byref(d), ctypes.byref(d), 24, FAKE, None) == adct.E_SHAPE
     assert lib.adct_zonal_recon(FAKE, 4, ctypes.byref(d), ctypes.byref(d), 48, FAKE, None) == adct.E_SHAPE
     assert lib.adct_sse(ctypes.byref(d), ctypes.byref(r_bad), 16, FAKE, None) == adct.E_SHAPE
+
+
+# ---- host work-queue construction (no GPU) ----
+def test_work_queue_small_exact():
+    items = adct.work_queue([5, 0, 33], tiles_per_group=8, groups_per_item=2)
+    assert items.tolist() == [[0, 0, 5], [2, 0, 16], [2, 16, 16], [2, 32, 1]]
+
+
+def test_work_queue_covers_every_tile_once():
+    rng = np.random.default_rng(4)
+    tiles = rng.integers(1, 3000, size=200)
+    for tpg, gpi in [(8, 1), (16, 4), (32, 64)]:
+        items = adct.work_queue(tiles, tpg, gpi).astype(np.int64)
+        span = tpg * gpi
+        assert np.all(items[:, 2] >= 1) and np.all(items[:, 2] <= span)
+        assert np.all(items[:, 1] % span == 0)  # items start on whole groups
+        for j in range(len(tiles)):
+            mine = items[items[:, 0] == j]
+            covered = np.zeros(tiles[j], dtype=np.int64)
+            for _, first, cnt in mine:
+                covered[first:first + cnt] += 1
+            assert np.all(covered == 1)
+        assert np.all(np.diff(items[:, 0]) >= 0)  # job order
+
+
+def test_work_queue_errors():
+    lib = adct.lib()
+    n = ctypes.c_int64(0)
+    t = np.array([10, 20], dtype=np.int64)
+    assert lib.adct_work_queue(t.ctypes.data, 2, 0, 1, None, 0, ctypes.byref(n)) == adct.E_ARG
+    assert lib.adct_work_queue(t.ctypes.data, 2, 16, 0, None, 0, ctypes.byref(n)) == adct.E_ARG
+    bad = np.array([-1], dtype=np.int64)
+    assert lib.adct_work_queue(bad.ctypes.data, 1, 16, 1, None, 0, ctypes.byref(n)) == adct.E_ARG
+    out = np.zeros(3, dtype=np.uint32)
+    assert lib.adct_work_queue(t.ctypes.data, 2, 16, 1, out.ctypes.data, 1, ctypes.byref(n)) == adct.E_TOO_LARGE
+    assert n.value == 3  # 10 tiles -> 1 item, 20 tiles -> 2 items of at most 16
+
+
+def test_default_tune_and_batch_arg_checks():
+    t = adct.default_tune()
+    assert t.tiles_per_group in (8, 16, 32) and t.groups_per_item >= 1 and t.wgs_per_cu >= 1
+    lib = adct.lib()
+    h = ctypes.c_void_p()
+    jobs = (adct.Job * 1)()
+    jobs[0] = adct.Job(adct.Plane(FAKE, adct.U8, 24, 16, 0, 16), adct.Plane(FAKE, adct.U8, 24, 16, 0, 16), None, None)
+    assert lib.adct_batch_create(ctypes.byref(h), jobs, 1, adct.OP_ZONAL, 8, None) == adct.E_SHAPE
+    jobs[0] = adct.Job(adct.Plane(FAKE, adct.U8, 16, 16, 0, 16), adct.Plane(FAKE, adct.I16, 16, 16, 0, 32), None, None)
+    assert lib.adct_batch_create(ctypes.byref(h), jobs, 1, adct.OP_ZONAL, 8, None) == adct.E_SHAPE
+    jobs[0] = adct.Job(adct.Plane(FAKE, adct.U8, 16, 16, 0, 16), adct.Plane(FAKE, adct.U8, 16, 16, 0, 16), None, None)
+    assert lib.adct_batch_create(ctypes.byref(h), jobs, 1, adct.OP_ZONAL, 17, None) == adct.E_ARG
+    assert lib.adct_batch_create(ctypes.byref(h), jobs, 1, adct.OP_QUANT, 64, None) == adct.E_ARG
+    assert lib.adct_batch_create(ctypes.byref(h), jobs, 1, 9, 8, None) == adct.E_ARG
+    assert lib.adct_batch_create(ctypes.byref(h), jobs, 0, adct.OP_ZONAL, 8, None) == adct.E_ARG
+    bad = adct.make_tune(12, 1, 1)
+    # a bad tuning is rejected before any device work
+    assert lib.adct_batch_create(ctypes.byref(h), jobs, 1, adct.OP_ZONAL, 8, ctypes.byref(bad)) in (adct.E_ARG, adct.E_HIP)
+    assert lib.adct_batch_submit(None, None) == adct.E_ARG
+    assert lib.adct_batch_destroy(None) == adct.E_ARG
