@@ -267,6 +267,127 @@ int adct_batch_destroy(adct_batch* b);
 int adct_autotune(int32_t op, int32_t param, const adct_job* jobs, int32_t njobs, const char* cache_path,
                   int32_t reps, adct_tune* out, double* ms);
 
+/* ---- serving: continuous batching on a device-resident loop -------- */
+/* Requests (uint8 images of any size that is a multiple of 16, each coded as
+ * adct_encode_quant at the server's qp: levels and reconstruction kept on
+ * the device, exact SSE reported) arrive over time.  A host thread admits
+ * them in submission order when the server's device memory pool has room
+ * (and fewer than max_inflight are held), copies their pixels in, and
+ * publishes them to a persistent kernel.  That kernel's workgroups claim
+ * published work items (runs of tiles of one request) as they appear, so
+ * requests that arrive while others run are coded alongside them; the last
+ * workgroup to finish a request posts its SSE and a completion flag to host
+ * memory.  In ADCT_SERVE_PLAIN mode the same admission feeds a plain
+ * per-request path instead (one stream: copy, adct_fwd2d_quant,
+ * adct_dequant_recon, event), the baseline the persistent loop is measured
+ * against.  Results are bit-identical between modes and between a request
+ * coded alone and in any mix.  Times are in nanoseconds of the server clock
+ * (adct_now_ns). */
+
+#define ADCT_SERVE_PERSISTENT 0
+#define ADCT_SERVE_PLAIN      1
+
+typedef struct adct_server_cfg {
+    int64_t pool_bytes;      /* device pool for request data (4 bytes per pixel) */
+    int32_t qp;              /* quantiser for every request, [0, 63]            */
+    int32_t mode;            /* ADCT_SERVE_PERSISTENT or ADCT_SERVE_PLAIN       */
+    int32_t max_inflight;    /* admitted and not yet released, >= 1             */
+    int32_t max_requests;    /* requests over the server's lifetime, >= 1       */
+    int32_t auto_release;    /* 1: free a request's device data when it completes
+                                (its SSE and times stay readable)               */
+    int32_t tiles_per_item;  /* persistent: tiles per work item, a multiple of 16
+                                (0 = 128)                                        */
+    int32_t wgs_per_cu;      /* persistent: loop workgroups per CU (0 = 2)      */
+    int32_t idle_polls;      /* persistent: empty polls (about 3.4 us each) before
+                                an idle workgroup exits; the server relaunches the
+                                loop when work reappears (0 = 1000000)           */
+} adct_server_cfg;
+
+typedef struct adct_result {
+    int32_t status;          /* ADCT_OK, ADCT_PENDING or ADCT_E_STOPPED          */
+    int32_t height, width;
+    int32_t reserved;
+    void* dst;               /* device uint8 reconstruction [height][width]; NULL
+                                once released                                    */
+    void* q;                 /* device int16 levels [nblk][16][16]; NULL once released */
+    int64_t sse;             /* exact SSE of dst against the submitted pixels    */
+    int64_t t_arrival_ns;    /* when the request counts as arrived               */
+    int64_t t_admit_ns;      /* when it got pool memory and its copy was issued  */
+    int64_t t_done_ns;       /* when the server observed its completion          */
+} adct_result;
+
+typedef struct adct_stats {
+    int64_t submitted, admitted, completed, cancelled;
+    int64_t in_flight;       /* admitted and not yet completed                   */
+    int64_t tiles_completed;
+    int64_t pool_bytes, pool_high_water;
+    double wall_s;           /* first arrival to last completion                 */
+    double tiles_per_s;      /* tiles_completed / wall_s                         */
+    double latency_p50_ms, latency_p99_ms, latency_mean_ms, latency_max_ms;
+    double queue_p50_ms, queue_p99_ms;  /* arrival to admission                  */
+    int64_t loop_launches;   /* persistent loop (re)launches                     */
+} adct_stats;
+
+typedef struct adct_server adct_server;
+
+/* Server clock (monotonic, ns). */
+int64_t adct_now_ns(void);
+
+/* Allocates the pool and the server's device state, starts its host thread
+ * (and, in persistent mode, the device loop) on the current device. */
+int adct_server_create(adct_server** out, const adct_server_cfg* cfg);
+
+/* Queues one request.  host_pixels: uint8 [height][pitch_bytes] in host
+ * memory (pinned memory gives asynchronous copies), which must stay valid
+ * until the request completes.  arrival_ns < 0 means now; a later time holds
+ * the request back until then (open-loop replay).  Requests are admitted in
+ * submission order.  ADCT_E_TOO_LARGE when the request can never fit the
+ * pool (4 * height * width bytes) or max_requests is used up. */
+int adct_server_submit(adct_server* s, const void* host_pixels, int32_t height, int32_t width, int64_t pitch_bytes,
+                       int64_t arrival_ns, uint64_t* ticket);
+
+/* Non-blocking: ADCT_PENDING (> 0) until done, then ADCT_OK with *out
+ * filled; ADCT_E_STOPPED for a cancelled request, ADCT_E_NOTFOUND for an
+ * unknown ticket. */
+int adct_server_poll(adct_server* s, uint64_t ticket, adct_result* out);
+
+/* Blocks until every submitted request is done or cancelled, or until
+ * timeout_ns passes (ADCT_E_TIMEOUT). */
+int adct_server_wait_all(adct_server* s, int64_t timeout_ns);
+
+/* Returns a completed request's device memory to the pool. */
+int adct_server_release(adct_server* s, uint64_t ticket);
+
+int adct_server_stats(adct_server* s, adct_stats* out);
+
+/* drain = 1: finish every submitted request first; 0: cancel those not yet
+ * admitted (admitted ones still finish).  Then stops the device loop. */
+int adct_server_stop(adct_server* s, int32_t drain);
+
+/* Stops (without draining) and frees everything. */
+int adct_server_destroy(adct_server* s);
+
+/* ---- the server's host policy, runnable without a GPU ------------------ */
+
+/* Replays a sequence on the server's pool allocator (first fit, 256-byte
+ * granules, coalescing) of the given capacity: ops[i] > 0 allocates that
+ * many bytes (out[i] = offset or -1); ops[i] <= 0 frees the block allocated
+ * by op -ops[i] (out[i] = 0).  *high_water (may be NULL) receives the peak
+ * bytes in use.  ADCT_E_ARG for a free of an unknown block. */
+int adct_pool_simulate(int64_t capacity, const int64_t* ops, int32_t nops, int64_t* out, int64_t* high_water);
+
+/* Replays the server's admission rule (submission order, the head blocks
+ * the rest; admitted when arrived, fewer than max_inflight held and the pool
+ * can place it) on a fake clock: request i arrives at arrival[i], needs
+ * bytes[i] and holds them for hold[i] after admission.  admit[i] receives
+ * its admission time.  ADCT_E_TOO_LARGE when a request can never fit. */
+int adct_admission_simulate(int64_t capacity, int32_t max_inflight, const int64_t* arrival, const int64_t* bytes,
+                            const int64_t* hold, int32_t n, int64_t* admit);
+
+/* Nearest-rank percentile p in [0, 100] of n values (the latency statistic
+ * the server reports). */
+int adct_percentile(const double* v, int64_t n, double p, double* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -46,6 +46,34 @@ class Tune(ctypes.Structure):
 
 
 OP_ZONAL, OP_QUANT = 1, 2
+SERVE_PERSISTENT, SERVE_PLAIN = 0, 1
+
+
+class ServerCfg(ctypes.Structure):
+    _fields_ = [("pool_bytes", ctypes.c_int64), ("qp", ctypes.c_int32), ("mode", ctypes.c_int32),
+                ("max_inflight", ctypes.c_int32), ("max_requests", ctypes.c_int32),
+                ("auto_release", ctypes.c_int32), ("tiles_per_item", ctypes.c_int32),
+                ("wgs_per_cu", ctypes.c_int32), ("idle_polls", ctypes.c_int32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("height", ctypes.c_int32), ("width", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("dst", ctypes.c_void_p), ("q", ctypes.c_void_p),
+                ("sse", ctypes.c_int64), ("t_arrival_ns", ctypes.c_int64), ("t_admit_ns", ctypes.c_int64),
+                ("t_done_ns", ctypes.c_int64)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("admitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("cancelled", ctypes.c_int64), ("in_flight", ctypes.c_int64), ("tiles_completed", ctypes.c_int64),
+                ("pool_bytes", ctypes.c_int64), ("pool_high_water", ctypes.c_int64), ("wall_s", ctypes.c_double),
+                ("tiles_per_s", ctypes.c_double), ("latency_p50_ms", ctypes.c_double),
+                ("latency_p99_ms", ctypes.c_double), ("latency_mean_ms", ctypes.c_double),
+                ("latency_max_ms", ctypes.c_double), ("queue_p50_ms", ctypes.c_double),
+                ("queue_p99_ms", ctypes.c_double), ("loop_launches", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 _P = ctypes.c_void_p
 _PP = ctypes.POINTER(Plane)
@@ -80,6 +108,18 @@ _SIGNATURES = {
     "adct_batch_destroy": (ctypes.c_int, [_P]),
     "adct_autotune": (ctypes.c_int, [_I32, _I32, ctypes.POINTER(Job), _I32, ctypes.c_char_p, _I32,
                                      ctypes.POINTER(Tune), ctypes.POINTER(_D)]),
+    "adct_now_ns": (ctypes.c_int64, []),
+    "adct_server_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.POINTER(ServerCfg)]),
+    "adct_server_submit": (ctypes.c_int, [_P, _P, _I32, _I32, _I64, _I64, ctypes.POINTER(ctypes.c_uint64)]),
+    "adct_server_poll": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.POINTER(Result)]),
+    "adct_server_wait_all": (ctypes.c_int, [_P, _I64]),
+    "adct_server_release": (ctypes.c_int, [_P, ctypes.c_uint64]),
+    "adct_server_stats": (ctypes.c_int, [_P, ctypes.POINTER(Stats)]),
+    "adct_server_stop": (ctypes.c_int, [_P, _I32]),
+    "adct_server_destroy": (ctypes.c_int, [_P]),
+    "adct_pool_simulate": (ctypes.c_int, [_I64, _P, _I32, _P, ctypes.POINTER(_I64)]),
+    "adct_admission_simulate": (ctypes.c_int, [_I64, _I32, _P, _P, _P, _I32, _P]),
+    "adct_percentile": (ctypes.c_int, [_P, _I64, _D, ctypes.POINTER(_D)]),
 }
 
 _LIB = None
@@ -403,3 +443,108 @@ def autotune(srcs, dsts, op: int, param: int, coefs=None, sses=None, cache_path=
     _check(_lib().adct_autotune(op, param, jobs, len(jobs), cache_path.encode() if cache_path else None, reps,
                                 ctypes.byref(t), ctypes.byref(ms)), "autotune")
     return t, ms.value
+
+
+# ---------------------------------------------------------------- serving
+def now_ns() -> int:
+    return _lib().adct_now_ns()
+
+
+class Server:
+    """Continuous-batching server (persistent device loop) or the plain
+    per-request baseline (mode=SERVE_PLAIN).  Submitted host buffers are kept
+    referenced until the server is closed."""
+
+    def __init__(self, pool_bytes: int, qp: int = 27, mode: int = SERVE_PERSISTENT, max_inflight: int = 64,
+                 max_requests: int = 4096, auto_release: bool = False, tiles_per_item: int = 0,
+                 wgs_per_cu: int = 0, idle_polls: int = 0):
+        cfg = ServerCfg(pool_bytes, qp, mode, max_inflight, max_requests, 1 if auto_release else 0, tiles_per_item,
+                        wgs_per_cu, idle_polls)
+        h = _P()
+        _check(_lib().adct_server_create(ctypes.byref(h), ctypes.byref(cfg)), "server_create")
+        self._h = h
+        self._keep = []
+
+    def submit(self, pixels, arrival_ns: int = -1) -> int:
+        """pixels: a 2D uint8 host tensor or numpy array (pinned for asynchronous copies)."""
+        if hasattr(pixels, "data_ptr"):
+            ptr, (h, w), pitch = pixels.data_ptr(), pixels.shape, pixels.stride(0)
+        else:
+            ptr, (h, w), pitch = pixels.ctypes.data, pixels.shape, pixels.strides[0]
+        t = ctypes.c_uint64(0)
+        _check(_lib().adct_server_submit(self._h, ptr, h, w, pitch, arrival_ns, ctypes.byref(t)), "server_submit")
+        self._keep.append(pixels)
+        return t.value
+
+    def poll(self, ticket: int):
+        """(status, Result): status is OK, PENDING, E_STOPPED or E_NOTFOUND."""
+        r = Result()
+        rc = _lib().adct_server_poll(self._h, ticket, ctypes.byref(r))
+        if rc < 0 and rc not in (E_STOPPED, E_NOTFOUND):
+            raise AdctError(rc, "server_poll")
+        return rc, r
+
+    def wait_all(self, timeout_s: float = 60.0):
+        _check(_lib().adct_server_wait_all(self._h, int(timeout_s * 1e9)), "server_wait_all")
+
+    def release(self, ticket: int):
+        _check(_lib().adct_server_release(self._h, ticket), "server_release")
+
+    def stats(self) -> dict:
+        st = Stats()
+        _check(_lib().adct_server_stats(self._h, ctypes.byref(st)), "server_stats")
+        return st.as_dict()
+
+    def stop(self, drain: bool = True):
+        _check(_lib().adct_server_stop(self._h, 1 if drain else 0), "server_stop")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(_lib().adct_server_destroy(self._h), "server_destroy")
+            self._h = None
+            self._keep = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class _DeviceArray:
+    def __init__(self, ptr: int, shape, typestr: str):
+        self.__cuda_array_interface__ = {"shape": tuple(shape), "typestr": typestr, "data": (ptr, False),
+                                         "version": 2}
+
+
+def device_view(ptr: int, shape, dtype):
+    """A torch tensor aliasing server-owned device memory (valid until release)."""
+    torch = _torch()
+    typestr = {torch.uint8: "|u1", torch.int16: "<i2", torch.int32: "<i4"}[dtype]
+    return torch.as_tensor(_DeviceArray(ptr, shape, typestr), device="cuda")
+
+
+def pool_simulate(capacity: int, ops):
+    ops = np.ascontiguousarray(np.asarray(ops, dtype=np.int64))
+    out = np.empty(ops.shape[0], dtype=np.int64)
+    hw = _I64(0)
+    _check(_lib().adct_pool_simulate(capacity, ops.ctypes.data, ops.shape[0], out.ctypes.data, ctypes.byref(hw)),
+           "pool_simulate")
+    return out, hw.value
+
+
+def admission_simulate(capacity: int, max_inflight: int, arrival, nbytes, hold):
+    a = np.ascontiguousarray(np.asarray(arrival, dtype=np.int64))
+    b = np.ascontiguousarray(np.asarray(nbytes, dtype=np.int64))
+    h = np.ascontiguousarray(np.asarray(hold, dtype=np.int64))
+    out = np.empty(a.shape[0], dtype=np.int64)
+    _check(_lib().adct_admission_simulate(capacity, max_inflight, a.ctypes.data, b.ctypes.data, h.ctypes.data,
+                                          a.shape[0], out.ctypes.data), "admission_simulate")
+    return out
+
+
+def percentile(values, p: float) -> float:
+    v = np.ascontiguousarray(np.asarray(values, dtype=np.float64))
+    out = _D(0.0)
+    _check(_lib().adct_percentile(v.ctypes.data, v.shape[0], p, ctypes.byref(out)), "percentile")
+    return out.value

@@ -10,13 +10,13 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libadct.so")
 
-SOURCES = ["adct_host.cpp", "adct_plain.hip", "adct_batch.hip"]
+SOURCES = ["adct_host.cpp", "adct_plain.hip", "adct_batch.hip", "adct_server.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
     # packed-FP32 instructions are kept out of generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-Wall", "-Wno-unused-function",
+    "-Wall", "-Wno-unused-function", "-pthread",
 ]
 
 

@@ -63,7 +63,8 @@ __global__ __launch_bounds__(TPW * 8) void k_batch(BatchArgs b) {
             if (k) __syncthreads();
             const uint32_t g0n = g0 + (uint32_t)TPW;
             const uint32_t ntn = g0n < gend ? min((uint32_t)TPW, gend - g0n) : 0u;
-            process_group<TPW, S, M>(a, g0, min((uint32_t)TPW, gend - g0), lds, red, acc, rows, g0n, ntn);
+            process_group<TPW, S, M>(a, g0, min((uint32_t)TPW, gend - g0), lds, red, acc, rows, g0n, ntn, a.qs,
+                                     a.dqs);
         }
         if (a.sse) sse_flush<TPW * 8>(acc, a.sse, red);
       }

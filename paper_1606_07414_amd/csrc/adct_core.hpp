@@ -422,10 +422,12 @@ __device__ __forceinline__ void load_group_rows(const GroupArgs& a, uint32_t g0,
 // `rows` holds this group's input rows (forward modes); once they are
 // consumed, the rows of the next group (g0n, ntn; ntn = 0 for none) are
 // requested into it, so their latency overlaps this group's remaining work.
+// `qs`, `dqs` must refer to kernel-argument or global memory: the per-class
+// selects in column_factors may be compiled into indexed loads.
 template <int TPW, typename S, typename M>
 __device__ __forceinline__ void process_group(const GroupArgs& a, uint32_t g0, uint32_t ntile,
                                               uint32_t* lds, long long* red, SseAcc& acc, RowWords& rows,
-                                              uint32_t g0n, uint32_t ntn) {
+                                              uint32_t g0n, uint32_t ntn, const Scale5& qs, const Scale5& dqs) {
     const int tid = threadIdx.x;
     const int rlt = tid % TPW, rip = tid / TPW;     // row role
     const int clt = tid >> 3, cp = tid & 7;         // column role
@@ -478,7 +480,7 @@ __device__ __forceinline__ void process_group(const GroupArgs& a, uint32_t g0, u
     }
     if constexpr (M::MID == kMidQuant) {
         int32_t qa[16], qb[16];
-        quant_cols(a.qs, cp, ya, yb, qa, qb);
+        quant_cols(qs, cp, ya, yb, qa, qb);
         if constexpr (M::STORE == kStoreQ) {
             if (a.cout) {
                 __syncthreads();
@@ -493,10 +495,10 @@ __device__ __forceinline__ void process_group(const GroupArgs& a, uint32_t g0, u
                 ya[u] = qa[u];
                 yb[u] = qb[u];
             }
-            dequant_cols(a.dqs, cp, ya, yb);
+            dequant_cols(dqs, cp, ya, yb);
         }
     } else if constexpr (M::MID == kMidDequant) {
-        dequant_cols(a.dqs, cp, ya, yb);
+        dequant_cols(dqs, cp, ya, yb);
     } else if constexpr (M::MID == kMidZonal) {
         zonal_weights_cols<M::ZR>(cp, a.r, ya, yb);
     }
@@ -596,7 +598,7 @@ __global__ __launch_bounds__(TPW * 8) void k_group(GroupArgs a, uint32_t nblk, u
         if (k) __syncthreads();  // the previous group's LDS reads are done
         const uint32_t g0n = g0 + (uint32_t)TPW;
         const uint32_t ntn = g0n < gend ? min((uint32_t)TPW, gend - g0n) : 0u;
-        process_group<TPW, S, M>(a, g0, min((uint32_t)TPW, nblk - g0), lds, red, acc, rows, g0n, ntn);
+        process_group<TPW, S, M>(a, g0, min((uint32_t)TPW, nblk - g0), lds, red, acc, rows, g0n, ntn, a.qs, a.dqs);
     }
     if constexpr (M::SSE) {
         if (a.sse) sse_flush<TPW * 8>(acc, a.sse, red);

@@ -1,4 +1,5 @@
-// Element-wise coefficient-domain kernels, the plane SSE and small fills.
+// Element-wise coefficient-domain kernels, the plane SSE and small fills
+// (non-template kernels: include from one translation unit only).
 #pragma once
 
 #include <hip/hip_runtime.h>
