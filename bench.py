@@ -34,6 +34,8 @@ HBM_PEAK_GBS = 8000.0
 ENC_BYTES_PER_TILE = 256 + 1024 + 256     # u8 tile in, int32 coefficients out, u8 reconstruction out
 FWD_BYTES_PER_TILE = 256 + 1024           # two-kernel path: forward
 CPU_MIN_SECONDS = 10.0
+SERVE_TILES_PER_ITEM = 32    # persistent server: tiles per work item
+SERVE_WGS_PER_CU = 4         # persistent server: loop workgroups per CU
 
 
 def recon_bytes_per_tile(r: int) -> int:
@@ -49,7 +51,166 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--images", type=int, default=N_IMG)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-other", action="store_true", help="only the batched-image workload")
+    ap.add_argument("--serve-requests", type=int, default=2000)
     return ap.parse_args()
+
+
+def timed(torch, fn, reps, stream):
+    """Average ms of `reps` back-to-back calls of fn, HIP events on `stream`."""
+    fn()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def single_image(torch, adct, stream):
+    """One 256x256 image (256 tiles): per-call latency of the plain calls and
+    the S-scaled coefficient PSNR against the float64 exact DCT."""
+    import synth
+    from oracle import metrics as M
+    from oracle import adct_oracle as O
+    img = synth.ar1_image(synth.SEED_SINGLE, 256, 256)
+    x = torch.from_numpy(img).cuda()
+    out = torch.empty_like(x)
+    coef = adct.fwd2d(x)
+    res = {"tiles": 256,
+           "fwd2d_us": 1e3 * timed(torch, lambda: adct.fwd2d(x, coef, stream=stream), 200, stream),
+           "encode_zonal_r8_us": 1e3 * timed(torch, lambda: adct.encode_zonal(x, 8, out, coef=coef, stream=stream),
+                                             200, stream),
+           "inv2d_us": 1e3 * timed(torch, lambda: adct.inv2d(coef, stream=stream), 200, stream)}
+    B = adct.scale(adct.fwd2d(x)).cpu().numpy().astype(np.float64)
+    res["psnr_coef_vs_exact_dct_db"] = M.coefficient_psnr(B, M.exact_dct2d_tiles(O.to_tiles(img)))
+    return res
+
+
+def video(torch, adct, stream, frames=64):
+    """64 residual frames of 1920x1088 4:2:0 (Laplacian, scale 8): per QP the
+    single-pass encoder (levels + reconstruction + per-frame SSE) and the
+    two-kernel path, over all three planes."""
+    import synth
+    planes = [[], [], []]
+    for f in range(frames):
+        for i, p in enumerate(synth.video_frame_planes(f)):
+            planes[i].append(p)
+    xs = [torch.from_numpy(np.concatenate(p)).cuda() for p in planes]
+    heights = [1088, 544, 544]
+    tiles = sum(x.numel() // 256 for x in xs)
+    outs = [torch.empty_like(x) for x in xs]
+    qs = [torch.empty((x.numel() // 256, 16, 16), dtype=torch.int16, device="cuda") for x in xs]
+    sses = [torch.empty(frames, dtype=torch.int64, device="cuda") for _ in xs]
+    res = {"frames": frames, "tiles": tiles, "bytes_per_tile_fused": 1536, "qp": {}}
+    for qp in (22, 27, 32, 37):
+        def fused():
+            for x, o, q, s, h in zip(xs, outs, qs, sses, heights):
+                adct.encode_quant(x, qp, o, q=q, image_height=h, sse=s, stream=stream)
+
+        def two_pass():
+            for x, o, q, s, h in zip(xs, outs, qs, sses, heights):
+                adct.fwd2d_quant(x, qp, q, stream=stream)
+                adct.dequant_recon(q, qp, o, ref=x, image_height=h, sse=s, stream=stream)
+        ms_f = timed(torch, fused, 10, stream)
+        ms_t = timed(torch, two_pass, 10, stream)
+        fused()
+        sse = [s.cpu().numpy().astype(np.float64) for s in sses]
+        npix = [1088 * 1920, 544 * 960, 544 * 960]
+        psnr = [10 * np.log10(255.0 ** 2 * n / np.maximum(e, 1)) for e, n in zip(sse, npix)]
+        res["qp"][qp] = {"fused_ms": ms_f, "fused_tiles_per_s": tiles / (ms_f * 1e-3),
+                         "fused_gbs": 1536 * tiles / (ms_f * 1e-3) / 1e9,
+                         "two_kernel_ms": ms_t, "two_kernel_tiles_per_s": tiles / (ms_t * 1e-3),
+                         "psnr_y_u_v_db": [float(np.mean(p)) for p in psnr],
+                         "psnr_yuv_6_1_1_db": float(np.mean((6 * psnr[0] + psnr[1] + psnr[2]) / 8))}
+    return res
+
+
+def uneven_batch(torch, adct, stream, n=4096):
+    """4096 uint8 images with sides uniform over the multiples of 16 in
+    [64, 2048], coded by one persistent, graph-captured launch (autotuned):
+    coefficients, zonal r = 8 reconstruction and per-image SSE."""
+    import tempfile
+    import synth
+    sizes = synth.uneven_sizes(n)
+    pool = synth.crop_pool()
+    xs = [torch.from_numpy(np.ascontiguousarray(synth.crop_from_pool(pool, k, h, w))).cuda()
+          for k, (h, w) in enumerate(sizes)]
+    dsts = [torch.empty_like(x) for x in xs]
+    coefs = [torch.empty((x.numel() // 256, 16, 16), dtype=torch.int32, device="cuda") for x in xs]
+    sse = torch.empty(n, dtype=torch.int64, device="cuda")
+    sses = [sse[k:k + 1] for k in range(n)]
+    tiles = sum(x.numel() // 256 for x in xs)
+    cache = os.path.join(tempfile.gettempdir(), "adct_tune_cache.jsonl")
+    t0 = time.perf_counter()
+    tune, tune_ms = adct.autotune(xs, dsts, adct.OP_ZONAL, 8, coefs=coefs, sses=sses, cache_path=cache, reps=3)
+    tune_s = time.perf_counter() - t0
+    b = adct.Batch(xs, dsts, adct.OP_ZONAL, 8, coefs=coefs, sses=sses, tune=tune)
+    bd = adct.Batch(xs, dsts, adct.OP_ZONAL, 8, coefs=coefs, sses=sses)
+    ms = timed(torch, lambda: b.submit(stream), 10, stream)
+    ms_default = timed(torch, lambda: bd.submit(stream), 10, stream)
+    gbs = 1536 * tiles / (ms * 1e-3) / 1e9
+    out = {"images": n, "tiles": tiles, "tune": tune.as_dict(), "autotune_s": tune_s, "ms": ms,
+           "tiles_per_s": tiles / (ms * 1e-3), "gbs": gbs, "frac_of_8tbs": gbs / HBM_PEAK_GBS,
+           "default_tune_ms": ms_default, "items": b.info()["items"]}
+    b.close()
+    bd.close()
+    return out
+
+
+def serving(torch, adct, n_req, rates=(200, 500, 1000, 2000, 5000), warm=100):
+    """Poisson arrivals of uint8 AR(1) requests with sides log-uniform in
+    [256, 4096]; fwd + quant (QP 27) + dequant + inverse kept on the device.
+    The continuous-batching server against the plain per-request launch;
+    latency = arrival to observed completion, the first `warm` discarded."""
+    import synth
+    side_pool = 4096
+    pool = np.stack([synth.ar1_image(synth.SEED_REQ_CONTENT + i, side_pool, side_pool) for i in range(4)])
+    sides = synth.request_sides(n_req)
+    # one contiguous pinned buffer per distinct side (a crop of a pool image);
+    # requests of equal side share it (read only)
+    rng = np.random.default_rng(synth.SEED_REQ_CONTENT)
+    bufs = {}
+    for s in sorted(set(int(v) for v in sides)):
+        p, y, x = int(rng.integers(0, 4)), int(rng.integers(0, side_pool - s + 1)), int(rng.integers(0, side_pool - s + 1))
+        bufs[s] = torch.from_numpy(np.ascontiguousarray(pool[p, y:y + s, x:x + s])).pin_memory()
+    views = [bufs[int(s)] for s in sides]
+    tiles = np.array([int(s) * int(s) // 256 for s in sides])
+    # host-to-device copy rate of one large request from pinned memory (context)
+    big = bufs[max(bufs)]
+    dst = torch.empty(big.shape, dtype=torch.uint8, device="cuda")
+    cs = torch.cuda.Stream()
+    with torch.cuda.stream(cs):
+        ms = timed(torch, lambda: dst.copy_(big, non_blocking=True), 10, cs)
+    out = {"requests": n_req, "warmup_discarded": warm, "mean_tiles_per_request": float(tiles.mean()),
+           "h2d_gbs_pinned": big.numel() / (ms * 1e-3) / 1e9, "tiles_per_item": SERVE_TILES_PER_ITEM,
+           "wgs_per_cu": SERVE_WGS_PER_CU, "rate": {}}
+    for lam in rates:
+        arr = synth.poisson_arrivals(float(lam), n_req)
+        row = {}
+        for name, mode in (("persistent", adct.SERVE_PERSISTENT), ("plain", adct.SERVE_PLAIN)):
+            srv = adct.Server(pool_bytes=16 << 30, qp=27, mode=mode, max_inflight=512, max_requests=n_req,
+                              auto_release=True, tiles_per_item=SERVE_TILES_PER_ITEM, wgs_per_cu=SERVE_WGS_PER_CU)
+            t0 = adct.now_ns() + 20_000_000
+            tickets = [srv.submit(v, t0 + int(a * 1e9)) for v, a in zip(views, arr)]
+            srv.wait_all(600)
+            lat, first, last = [], None, None
+            for k, t in enumerate(tickets):
+                rc, r = srv.poll(t)
+                if k < warm:
+                    continue
+                lat.append((r.t_done_ns - r.t_arrival_ns) * 1e-6)
+                first = r.t_arrival_ns if first is None else min(first, r.t_arrival_ns)
+                last = r.t_done_ns if last is None else max(last, r.t_done_ns)
+            st = srv.stats()
+            srv.close()
+            row[name] = {"p50_ms": adct.percentile(lat, 50), "p99_ms": adct.percentile(lat, 99),
+                         "mean_ms": float(np.mean(lat)),
+                         "tiles_per_s": float(tiles[warm:].sum() / ((last - first) * 1e-9)),
+                         "loop_launches": st["loop_launches"], "pool_high_water": st["pool_high_water"]}
+        out["rate"][lam] = row
+    return out
 
 
 def cpu_baseline(img: np.ndarray):
@@ -168,6 +329,20 @@ def main():
         "psnr_db_mean": psnr,
         "input_gen_s": gen_s,
     }
+    if not args.no_other:
+        del coef, out, sse
+        torch.cuda.empty_cache()
+        other = {}
+        for name, fn in (("single_image_256x256", lambda: single_image(torch, adct, stream)),
+                         ("video_residuals_64x1920x1088", lambda: video(torch, adct, stream)),
+                         ("uneven_batch_4096", lambda: uneven_batch(torch, adct, stream)),
+                         ("serving_poisson", lambda: serving(torch, adct, args.serve_requests))):
+            t0 = time.perf_counter()
+            other[name] = fn()
+            other[name]["wall_s"] = time.perf_counter() - t0
+            torch.cuda.empty_cache()
+            print(f"[bench] {name} done in {other[name]['wall_s']:.1f} s", file=sys.stderr, flush=True)
+        result["other_workloads"] = other
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(img)
     print(json.dumps(result), flush=True)

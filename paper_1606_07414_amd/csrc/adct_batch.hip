@@ -42,16 +42,26 @@ __global__ __launch_bounds__(TPW * 8) void k_batch(BatchArgs b) {
     __shared__ uint32_t lds[lds_words(TPW)];
     __shared__ long long red[TPW * 8 / 64];
     __shared__ uint32_t claim;
+    const int tid = threadIdx.x;
     const uint32_t home = blockIdx.x % kQueues;
-    for (uint32_t qi = 0; qi < kQueues; ++qi) {
-      const uint32_t q = (home + qi) % kQueues;
-      const uint32_t base = b.qbeg[q], cnt = b.qbeg[q + 1] - base;
-      for (;;) {
-        __syncthreads();  // the previous item's LDS use and claim read are done
-        if (threadIdx.x == 0) claim = atomicAdd(b.heads + q * kHeadStride, 1u);
-        __syncthreads();
+    uint32_t qi = 0, q = home;
+    if (tid == 0) claim = atomicAdd(b.heads + q * kHeadStride, 1u);
+    __syncthreads();
+    for (;;) {
         const uint32_t c = __builtin_amdgcn_readfirstlane(claim);
-        if (c >= cnt) break;
+        const uint32_t base = b.qbeg[q], cnt = b.qbeg[q + 1] - base;
+        if (c >= cnt) {
+            // sub-queue q is drained: move to the next one
+            if (++qi >= kQueues) break;
+            q = (home + qi) % kQueues;
+            __syncthreads();  // every thread has read `claim`
+            if (tid == 0) claim = atomicAdd(b.heads + q * kHeadStride, 1u);
+            __syncthreads();
+            continue;
+        }
+        // claim the next item now; the atomic's latency overlaps this item
+        uint32_t next = 0;
+        if (tid == 0) next = atomicAdd(b.heads + q * kHeadStride, 1u);
         const ItemDev item = b.items[base + c];
         const GroupArgs& a = b.jobs[item.job];
         const uint32_t gend = item.first + item.count;
@@ -67,7 +77,9 @@ __global__ __launch_bounds__(TPW * 8) void k_batch(BatchArgs b) {
                                      a.dqs);
         }
         if (a.sse) sse_flush<TPW * 8>(acc, a.sse, red);
-      }
+        __syncthreads();  // every thread has read `claim` and finished with LDS
+        if (tid == 0) claim = next;
+        __syncthreads();
     }
 }
 
