@@ -34,8 +34,8 @@ HBM_PEAK_GBS = 8000.0
 ENC_BYTES_PER_TILE = 256 + 1024 + 256     # u8 tile in, int32 coefficients out, u8 reconstruction out
 FWD_BYTES_PER_TILE = 256 + 1024           # two-kernel path: forward
 CPU_MIN_SECONDS = 10.0
-SERVE_TILES_PER_ITEM = 32    # persistent server: tiles per work item
-SERVE_WGS_PER_CU = 4         # persistent server: loop workgroups per CU
+SERVE_TILES_PER_ITEM = 0     # persistent server: tiles per work item (0: chosen per request)
+SERVE_WGS_PER_CU = 2         # persistent server: loop workgroups per CU
 
 
 def recon_bytes_per_tile(r: int) -> int:

@@ -272,35 +272,46 @@ int adct_autotune(int32_t op, int32_t param, const adct_job* jobs, int32_t njobs
  * adct_encode_quant at the server's qp: levels and reconstruction kept on
  * the device, exact SSE reported) arrive over time.  A host thread admits
  * them in submission order when the server's device memory pool has room
- * (and fewer than max_inflight are held), copies their pixels in, and
- * publishes them to a persistent kernel.  That kernel's workgroups claim
- * published work items (runs of tiles of one request) as they appear, so
- * requests that arrive while others run are coded alongside them; the last
- * workgroup to finish a request posts its SSE and a completion flag to host
- * memory.  In ADCT_SERVE_PLAIN mode the same admission feeds a plain
- * per-request path instead (one stream: copy, adct_fwd2d_quant,
- * adct_dequant_recon, event), the baseline the persistent loop is measured
- * against.  Results are bit-identical between modes and between a request
- * coded alone and in any mix.  Times are in nanoseconds of the server clock
- * (adct_now_ns). */
+ * (and fewer than max_inflight are held) and publishes each admitted request
+ * to a persistent kernel through host-mapped memory.  One wave of that
+ * kernel forwards new requests to its other workgroups, which claim work
+ * items (runs of tiles of one request) as they appear and read the pixels in
+ * place from the caller's pinned host memory (no copy ahead, no other
+ * stream), so requests that arrive while others run are coded alongside
+ * them; the last workgroup to finish a request posts its SSE and a
+ * completion flag to host memory.  In ADCT_SERVE_PLAIN mode the same
+ * admission feeds a plain per-request path instead (one stream, first in
+ * first out: copy in, adct_fwd2d_quant, adct_dequant_recon, SSE copy back,
+ * event), the baseline the persistent loop is measured against.  In both
+ * modes the host thread polls without sleeping while requests are
+ * outstanding or the next one is due within 200 us (it then keeps one CPU
+ * core busy).  While the persistent loop runs it occupies one hardware queue
+ * of the device; work on another stream that the runtime maps to the same
+ * queue waits until the loop ends (after idle_polls empty polls).  Results
+ * are bit-identical between modes and between a request coded alone and in
+ * any mix.  Times are in nanoseconds of the server clock (adct_now_ns). */
 
 #define ADCT_SERVE_PERSISTENT 0
 #define ADCT_SERVE_PLAIN      1
 
 typedef struct adct_server_cfg {
-    int64_t pool_bytes;      /* device pool for request data (4 bytes per pixel) */
+    int64_t pool_bytes;      /* device pool for request data: 3 bytes per pixel
+                                (persistent: levels, reconstruction), 4 (plain:
+                                also the copied source)                          */
     int32_t qp;              /* quantiser for every request, [0, 63]            */
     int32_t mode;            /* ADCT_SERVE_PERSISTENT or ADCT_SERVE_PLAIN       */
     int32_t max_inflight;    /* admitted and not yet released, >= 1             */
     int32_t max_requests;    /* requests over the server's lifetime, >= 1       */
     int32_t auto_release;    /* 1: free a request's device data when it completes
                                 (its SSE and times stay readable)               */
-    int32_t tiles_per_item;  /* persistent: tiles per work item, a multiple of 16
-                                (0 = 128)                                        */
+    int32_t tiles_per_item;  /* persistent: tiles per work item, a multiple of 16;
+                                0 = per request: 16 for up to 2048 tiles, then
+                                doubling up to 128 as the request grows          */
     int32_t wgs_per_cu;      /* persistent: loop workgroups per CU (0 = 2)      */
-    int32_t idle_polls;      /* persistent: empty polls (about 3.4 us each) before
-                                an idle workgroup exits; the server relaunches the
-                                loop when work reappears (0 = 1000000)           */
+    int32_t idle_polls;      /* persistent: consecutive empty polls of the
+                                dispatching wave (about 1-2 us each) before the
+                                loop ends; the server relaunches it when work
+                                reappears (0 = 100000)                           */
 } adct_server_cfg;
 
 typedef struct adct_result {
@@ -338,11 +349,14 @@ int64_t adct_now_ns(void);
 int adct_server_create(adct_server** out, const adct_server_cfg* cfg);
 
 /* Queues one request.  host_pixels: uint8 [height][pitch_bytes] in host
- * memory (pinned memory gives asynchronous copies), which must stay valid
- * until the request completes.  arrival_ns < 0 means now; a later time holds
- * the request back until then (open-loop replay).  Requests are admitted in
- * submission order.  ADCT_E_TOO_LARGE when the request can never fit the
- * pool (4 * height * width bytes) or max_requests is used up. */
+ * memory, which must stay valid and unchanged until the request completes.
+ * Persistent mode reads it in place: it must be pinned memory the device can
+ * address (hipHostMalloc, or a pinned torch tensor), else ADCT_E_ARG, with
+ * host_pixels and pitch_bytes multiples of 16 (else ADCT_E_ALIGN).  Plain
+ * mode copies it (pinned memory gives asynchronous copies).  arrival_ns < 0
+ * means now; a later time holds the request back until then (open-loop
+ * replay).  Requests are admitted in submission order.  ADCT_E_TOO_LARGE
+ * when the request can never fit the pool or max_requests is used up. */
 int adct_server_submit(adct_server* s, const void* host_pixels, int32_t height, int32_t width, int64_t pitch_bytes,
                        int64_t arrival_ns, uint64_t* ticket);
 

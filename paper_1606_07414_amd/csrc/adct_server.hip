@@ -1,30 +1,36 @@
 // Serving: continuous batching of uneven requests on a device-resident loop.
 //
-// Device state, all indexed by the request's sequence number k (= ticket - 1,
-// never reused within a server): a 128-byte descriptor, a claim counter, a
-// done counter and an SSE accumulator in device memory, and a completion
-// record in host-mapped memory.
+// Requests are identified by their sequence number k (= ticket - 1) and, once
+// admitted, by a publication slot j (slots are handed out in admission order;
+// neither is ever reused within a server).
 //
-// Publication: for each admitted request the host thread enqueues on one
-// copy stream (i) the pixels into the request's pool block, (ii) its
-// descriptor, (iii) the new count of published requests.  Stream order makes
-// the count visible only after the data it announces.
+// Publication.  The loop reads each request's pixels in place from the
+// caller's pinned host memory (over the host link, fused with the first
+// pass), so nothing is copied ahead and no other stream is involved.  For
+// each admitted request the host thread writes its 128-byte descriptor into
+// slot j of a ring in host-mapped memory and then stores j + 1 to a
+// host-mapped slot count (release order).  Results (levels and
+// reconstruction) go to the request's block of the device pool.
 //
-// Loop kernel (persistent, a few workgroups per CU): a workgroup scans
-// requests from the lowest one that may still have unclaimed items; for
-// request k < published it claims item g = atomicAdd(claim[k], 1) and codes
-// it when g < items(k), else marks k exhausted (atomicMax on the low mark)
-// and moves on.  Only published requests are touched and claim counters are
-// never reused, so an over-claim is harmless and no claim is ever left
-// pending.  Before reading a newly met request's descriptor and pixels the
-// workgroup takes a system-scope acquire fence, so that no cache line left
-// over from an earlier user of the same pool memory is read.  After coding
-// an item: release fence, then done[k] += 1; the workgroup that completes
-// request k posts its SSE and a completion flag (system scope) to host
-// memory.  An idle workgroup sleeps between polls and exits on the stop flag
-// or after `idle_polls` empty polls; the host relaunches the loop when
-// published work is outstanding and the loop has exited.
+// Loop kernel (persistent).  Workgroup 0 is the dispatcher: one wave polls
+// the host-mapped slot count, copies new descriptors into device memory and
+// then advances the device slot count (release).  Every other workgroup is a
+// worker: it scans slots from the lowest one that may still have unclaimed
+// items; for slot j < count it claims item g = atomicAdd(claim[j], 1) and
+// codes it when g < items(j), else marks j exhausted (atomicMax on the low
+// mark) and moves on.  Over-claims are harmless since claim counters are
+// never reused.  Before reading a newly met slot's descriptor and pixels a
+// worker takes a system-scope acquire fence, so that no cache line left over
+// from an earlier user of the same pool memory is read.  After coding an
+// item: release fence, then done[j] += 1; the worker that completes slot j
+// posts the SSE and a completion flag (system scope) to the host-mapped
+// record of request k.  The dispatcher ends the loop: on the host's stop
+// flag, or after `idle_polls` consecutive empty polls, it stores this
+// launch's epoch to the quit word; a worker leaves once it sees that word
+// and finds nothing left to claim.  The host relaunches the loop (with the
+// next epoch) when published work is outstanding and the loop has exited.
 #include <hip/hip_runtime.h>
+#include <sys/prctl.h>
 
 #include <chrono>
 #include <condition_variable>
@@ -39,14 +45,17 @@
 
 namespace adct {
 
-// One 128-byte line per request; the kernel reads it as 32 words.
+// One 128-byte line per publication slot; the kernel reads it as 16 words
+// of 8 bytes.
 struct ReqDesc {
     uint64_t src, dst, q;                     // words 0-5: device addresses in the pool
     uint32_t height, width;                   // 6, 7: samples
     uint32_t nitems, tiles_per_item;          // 8, 9
     uint32_t bw, bw_m, bw_s1, bw_s2;          // 10-13: tiles per row and its FastDiv
     uint32_t ipb_m, ipb_s1, ipb_s2, nblk;     // 14-17: FastDiv by height / 16, tiles
-    uint32_t pad[14];
+    uint32_t req;                             // 18: request sequence number
+    uint32_t src_pitch;                       // 19: bytes between source rows
+    uint32_t pad[12];
 };
 static_assert(sizeof(ReqDesc) == 128, "one descriptor per 128-byte line");
 
@@ -57,16 +66,20 @@ struct Completion {
 };
 
 struct ServeArgs {
-    const ReqDesc* desc;
-    const uint32_t* published;   // requests published so far (written by DMA)
-    uint32_t* low;               // every request below this is exhausted
-    uint32_t* claim;             // per request: items handed out (may overshoot)
-    uint32_t* done;              // per request: items finished
-    unsigned long long* sse;     // per request: SSE accumulator
+    const ReqDesc* h_desc;       // host-mapped descriptor ring, by slot
+    const uint32_t* h_count;     // host-mapped: slots written by the host
+    ReqDesc* desc;               // device copy of the ring (dispatcher writes)
+    uint32_t* count;             // slots copied to the device so far
+    uint32_t* low;               // every slot below this is exhausted
+    uint32_t* quit;              // epoch of the launch told to end
+    uint32_t* claim;             // per slot: items handed out (may overshoot)
+    uint32_t* done;              // per slot: items finished
+    unsigned long long* sse;     // per slot: SSE accumulator
     Completion* comp;            // per request, host-mapped
     const uint32_t* stop;        // host-mapped
     Scale5 qs, dqs;
     uint32_t idle_polls;
+    uint32_t epoch;
 };
 
 template <typename T>
@@ -89,13 +102,13 @@ __device__ __forceinline__ uint64_t rfl64(uint64_t v) {
 constexpr int kServeTPW = 16;
 using ServeMode = Mode<kInSamples, kStoreQ, kMidQuant, kOutSamples, -1, true>;
 
-// Group arguments of request k from its descriptor words (held in LDS).
-__device__ __forceinline__ GroupArgs args_from_desc(const uint64_t* sh_desc, const ServeArgs& s, uint32_t k) {
+// Group arguments of slot j from its descriptor words (held in LDS).
+__device__ __forceinline__ GroupArgs args_from_desc(const uint64_t* sh_desc, const ServeArgs& s, uint32_t j) {
     const uint32_t* w = reinterpret_cast<const uint32_t*>(sh_desc);
     const uint32_t width = rfl(w[7]), bw = rfl(w[10]);
     GroupArgs a{};
     a.src.data = global_ptr(rfl64(sh_desc[0]));
-    a.src.pitch = width;
+    a.src.pitch = rfl(w[19]);
     a.src.bw = bw;
     a.dst.data = global_ptr(rfl64(sh_desc[1]));
     a.dst.pitch = width;
@@ -104,72 +117,112 @@ __device__ __forceinline__ GroupArgs args_from_desc(const uint64_t* sh_desc, con
     a.bw = bw;
     a.bwdiv = FastDiv{rfl(w[11]), rfl(w[12]), rfl(w[13])};
     a.ipbdiv = FastDiv{rfl(w[14]), rfl(w[15]), rfl(w[16])};
-    a.sse = s.sse + k;
+    a.sse = s.sse + j;
     return a;
+}
+
+// Workgroup 0, first wave: mirrors host-published descriptors to the device.
+__device__ void serve_dispatch(const ServeArgs& s) {
+    const uint32_t lane = threadIdx.x;
+    uint32_t have = rfl(load_sys(s.count));
+    uint32_t idle = 0;
+    for (;;) {
+        const uint32_t c = rfl(load_sys(s.h_count));
+        if (c > have) {
+            // four descriptors per pass, 16 lanes x 8 bytes each
+            for (uint32_t j = have + lane / 16u; j < c; j += 4u) {
+                const uint64_t v = load_sys(reinterpret_cast<const uint64_t*>(s.h_desc + j) + (lane & 15u));
+                __hip_atomic_store(reinterpret_cast<uint64_t*>(s.desc + j) + (lane & 15u), v, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_SYSTEM);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");  // the wave's descriptor stores reach memory
+            // the count is advanced with an atomic: it is performed where every
+            // XCD's system-scope loads see it
+            if (lane == 0) atomicMax(s.count, c);
+            have = c;
+            idle = 0;
+            continue;
+        }
+        if ((idle & 63u) == 0u && rfl(load_sys(s.stop))) break;
+        if (++idle > s.idle_polls) break;  // watchdog: the host relaunches on demand
+        __builtin_amdgcn_s_sleep(16);
+    }
+    // after the last count update: a worker that sees the quit word also
+    // sees the final count
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+    if (lane == 0) atomicMax(s.quit, s.epoch);
 }
 
 __global__ __launch_bounds__(kServeTPW * 8) void k_serve(ServeArgs s) {
     constexpr int TPW = kServeTPW;
+    if (blockIdx.x == 0) {
+        if (threadIdx.x < 64) serve_dispatch(s);
+        return;
+    }
     __shared__ uint32_t lds[lds_words(TPW)];
     __shared__ long long red[TPW * 8 / 64];
-    __shared__ uint32_t sh_k, sh_g, sh_cursor, sh_stop;
-    __shared__ uint64_t sh_desc[16];  // descriptor of request `cur`
+    __shared__ uint32_t sh_j, sh_g, sh_cursor, sh_quit;
+    __shared__ uint64_t sh_desc[16];  // descriptor of slot `cur`
     const int tid = threadIdx.x;
     if (tid == 0) sh_cursor = 0;
     uint32_t cur = 0xffffffffu;
-    uint32_t idle = 0;
+    bool quit_seen = false;
     for (;;) {
         __syncthreads();  // the previous item is finished with LDS and sh_*
         if (tid == 0) {
-            uint32_t k = max(sh_cursor, __hip_atomic_load(s.low, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-            const uint32_t pub = load_sys(s.published);
-            uint32_t res_k = 0xffffffffu, res_g = 0;
-            while (k < pub) {
-                const uint32_t n = load_sys(&s.desc[k].nitems);
-                const uint32_t g = atomicAdd(s.claim + k, 1u);
+            uint32_t j = max(sh_cursor, load_sys(s.low));
+            const uint32_t cnt = load_sys(s.count);
+            uint32_t res_j = 0xffffffffu, res_g = 0;
+            while (j < cnt) {
+                const uint32_t n = load_sys(&s.desc[j].nitems);
+                const uint32_t g = atomicAdd(s.claim + j, 1u);
                 if (g < n) {
-                    res_k = k;
+                    res_j = j;
                     res_g = g;
                     break;
                 }
-                atomicMax(s.low, k + 1);
-                ++k;
+                atomicMax(s.low, j + 1);
+                ++j;
             }
-            sh_cursor = k;
-            sh_k = res_k;
+            sh_cursor = j;
+            sh_j = res_j;
             sh_g = res_g;
         }
         __syncthreads();
-        const uint32_t k = rfl(sh_k);
-        if (k == 0xffffffffu) {
-            if (tid == 0) sh_stop = (idle % 64u == 0u) ? load_sys(s.stop) : 0u;
+        const uint32_t j = rfl(sh_j);
+        if (j == 0xffffffffu) {
+            // nothing to claim: leave once the dispatcher has ended this
+            // launch and one more scan (after seeing that) found nothing
+            if (quit_seen) break;
+            if (tid == 0) sh_quit = load_sys(s.quit) == s.epoch;
             __syncthreads();
-            if (rfl(sh_stop)) break;
-            if (++idle > s.idle_polls) break;  // watchdog: the host relaunches on demand
-            __builtin_amdgcn_s_sleep(127);
+            if (rfl(sh_quit)) {
+                quit_seen = true;
+                continue;
+            }
+            __builtin_amdgcn_s_sleep(64);
             continue;
         }
-        idle = 0;
         const uint32_t g = rfl(sh_g);
-        if (k != cur) {
-            // first item of a request met by this workgroup: acquire, then read
+        if (j != cur) {
+            // first item of a slot met by this workgroup: acquire, then read
             // its descriptor past the caches
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
-            if (tid < 16) sh_desc[tid] = load_sys(reinterpret_cast<const uint64_t*>(s.desc + k) + tid);
+            if (tid < 16) sh_desc[tid] = load_sys(reinterpret_cast<const uint64_t*>(s.desc + j) + tid);
             __syncthreads();
-            cur = k;
+            cur = j;
         }
-        const GroupArgs a = args_from_desc(sh_desc, s, k);
+        const GroupArgs a = args_from_desc(sh_desc, s, j);
         const uint32_t* dw = reinterpret_cast<const uint32_t*>(sh_desc);
-        const uint32_t nitems = rfl(dw[8]), tpi = rfl(dw[9]), nblk = rfl(dw[17]);
+        const uint32_t nitems = rfl(dw[8]), tpi = rfl(dw[9]), nblk = rfl(dw[17]), req = rfl(dw[18]);
         const uint32_t t0 = g * tpi;
         const uint32_t gend = min(nblk, t0 + tpi);
         SseAcc acc{0, kNoImage};
         RowWords rows;
         uint32_t g0 = t0;
         load_group_rows<TPW, uint8_t>(a, g0, min((uint32_t)TPW, gend - g0), rows);
-        for (uint32_t j = 0; g0 < gend; ++j, g0 += (uint32_t)TPW) {
-            if (j) __syncthreads();
+        for (uint32_t i = 0; g0 < gend; ++i, g0 += (uint32_t)TPW) {
+            if (i) __syncthreads();
             const uint32_t g0n = g0 + (uint32_t)TPW;
             const uint32_t ntn = g0n < gend ? min((uint32_t)TPW, gend - g0n) : 0u;
             process_group<TPW, uint8_t, ServeMode>(a, g0, min((uint32_t)TPW, gend - g0), lds, red, acc, rows, g0n,
@@ -179,12 +232,12 @@ __global__ __launch_bounds__(kServeTPW * 8) void k_serve(ServeArgs s) {
         __syncthreads();
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // this item's outputs and SSE
         if (tid == 0) {
-            const uint32_t old = atomicAdd(s.done + k, 1u);
+            const uint32_t old = atomicAdd(s.done + j, 1u);
             if (old + 1u == nitems) {
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // every other item of k
-                const long long v = (long long)__hip_atomic_load(s.sse + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_store(&s.comp[k].sse, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-                __hip_atomic_store(&s.comp[k].flag, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // every other item of j
+                const long long v = (long long)load_sys(s.sse + j);
+                __hip_atomic_store(&s.comp[req].sse, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                __hip_atomic_store(&s.comp[req].flag, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
             }
         }
     }
@@ -202,6 +255,7 @@ enum ReqState { kWaiting = 0, kRunning = 1, kDone = 2, kReleased = 3, kCancelled
 
 struct Req {
     const void* host = nullptr;
+    uint64_t dev_src = 0;  // persistent: the host pixels' device-visible address
     int32_t h = 0, w = 0;
     int64_t pitch = 0;
     int64_t bytes = 0, tiles = 0;
@@ -209,8 +263,19 @@ struct Req {
     int64_t off = -1;
     int64_t sse = -1;
     int state = kWaiting;
-    int ev = -1;  // plain mode: event slot
+    int ev = -1;  // plain: event slot marking the end of the request
 };
+
+// Pool block of a request: persistent mode keeps reconstruction and levels
+// (3 bytes per pixel); plain mode also keeps the copied source in front of
+// them (4 bytes per pixel).
+struct Block {
+    char *src, *dst, *q;
+};
+
+// While requests are outstanding, or the next one arrives within this
+// window, the host thread polls instead of sleeping.
+constexpr int64_t kSpinWindowNs = 200000;
 
 }  // namespace
 }  // namespace adct
@@ -232,33 +297,37 @@ struct adct_server {
 
     std::vector<Req> reqs;
     int64_t head = 0, inflight = 0;
-    std::vector<int64_t> running;     // admitted, not yet done
-    int64_t n_done = 0, n_cancelled = 0, loop_launches = 0;
+    std::vector<int64_t> running;     // admitted, not yet done (plain: in stream order)
+    int64_t n_done = 0, n_cancelled = 0, loop_launches = 0, n_published = 0;
     int hip_error = 0;
+    uint32_t epoch = 0;
 
-    hipStream_t copy_stream = nullptr, loop_stream = nullptr;
+    hipStream_t stream = nullptr;     // the loop's stream, or the plain path's one stream
+    // plain mode
+    std::vector<hipEvent_t> events;
+    std::vector<int> free_events;
     // persistent mode
-    ReqDesc* d_desc = nullptr;
-    ReqDesc* h_desc = nullptr;        // pinned staging, one per request
-    uint32_t* h_pubvals = nullptr;    // pinned: value k + 1 published after request k
-    uint32_t* d_state = nullptr;      // published, low, then claim[n], done[n]
+    ReqDesc* h_desc = nullptr;        // host-mapped descriptor ring, by slot
+    ReqDesc* d_hdesc = nullptr;       // its device address
+    uint32_t* h_count = nullptr;      // host-mapped slot count
+    uint32_t* d_hcount = nullptr;
+    ReqDesc* d_desc = nullptr;        // device copy of the ring
+    uint32_t* d_state = nullptr;      // count, low, quit, then claim[n], done[n]
     unsigned long long* d_sse = nullptr;
-    Completion* h_comp = nullptr;     // host-mapped
+    Completion* h_comp = nullptr;     // host-mapped, by request
     Completion* d_comp = nullptr;     // its device address
     uint32_t* h_stop = nullptr;       // host-mapped
     uint32_t* d_stop = nullptr;
     hipEvent_t loop_done = nullptr;
-    // plain mode
-    std::vector<hipEvent_t> events;
-    std::vector<int> free_events;
 };
 
 namespace {
 
-uint32_t* st_published(adct_server* S) { return S->d_state; }
+uint32_t* st_count(adct_server* S) { return S->d_state; }
 uint32_t* st_low(adct_server* S) { return S->d_state + 32; }
-uint32_t* st_claim(adct_server* S) { return S->d_state + 64; }
-uint32_t* st_done(adct_server* S) { return S->d_state + 64 + S->cfg.max_requests; }
+uint32_t* st_quit(adct_server* S) { return S->d_state + 64; }
+uint32_t* st_claim(adct_server* S) { return S->d_state + 96; }
+uint32_t* st_done(adct_server* S) { return S->d_state + 96 + S->cfg.max_requests; }
 
 bool hip_ok(adct_server* S, hipError_t e) {
     if (e != hipSuccess && !S->hip_error) S->hip_error = (int)e;
@@ -267,9 +336,12 @@ bool hip_ok(adct_server* S, hipError_t e) {
 
 void launch_loop(adct_server* S) {
     ServeArgs a{};
+    a.h_desc = S->d_hdesc;
+    a.h_count = S->d_hcount;
     a.desc = S->d_desc;
-    a.published = st_published(S);
+    a.count = st_count(S);
     a.low = st_low(S);
+    a.quit = st_quit(S);
     a.claim = st_claim(S);
     a.done = st_done(S);
     a.sse = S->d_sse;
@@ -280,10 +352,12 @@ void launch_loop(adct_server* S) {
         a.dqs.f[c] = S->dqs.f[c];
     }
     a.idle_polls = (uint32_t)S->cfg.idle_polls;
-    hipLaunchKernelGGL(k_serve, dim3((unsigned)(S->cus * S->cfg.wgs_per_cu)), dim3(kServeTPW * 8), 0,
-                       S->loop_stream, a);
+    a.epoch = ++S->epoch;  // the quit word holds an older epoch, so this launch runs
+    // workgroup 0 dispatches, the rest code
+    hipLaunchKernelGGL(k_serve, dim3((unsigned)(S->cus * S->cfg.wgs_per_cu + 1)), dim3(kServeTPW * 8), 0,
+                       S->stream, a);
     hip_ok(S, hipGetLastError());
-    hip_ok(S, hipEventRecord(S->loop_done, S->loop_stream));
+    hip_ok(S, hipEventRecord(S->loop_done, S->stream));
     S->loop_running = true;
     ++S->loop_launches;
 }
@@ -299,38 +373,69 @@ bool loop_exited(adct_server* S) {
     return false;
 }
 
-PlaneRef plane_of(const char* p, int32_t w) {
-    PlaneRef r;
-    r.data = p;
-    r.pitch = w;
-    r.bw = (uint32_t)(w / 16);
-    return r;
+Block block_of(const adct_server* S, const Req& r) {
+    const int64_t plane = Pool::round_up((int64_t)r.h * r.w);
+    char* base = S->pool_mem + r.off;
+    Block b;
+    b.src = S->cfg.mode == ADCT_SERVE_PLAIN ? base : nullptr;
+    b.dst = S->cfg.mode == ADCT_SERVE_PLAIN ? base + plane : base;
+    b.q = b.dst + plane;
+    return b;
 }
 
-// Copies the request in and hands it to the device (called with mu held).
+// Tiles per work item of a request.  Adaptive (cfg value 0): small requests
+// are cut into 16-tile items so that many workgroups share them; larger ones
+// into items of up to 128 tiles (at most about 128 items for requests up to
+// 16384 tiles), which amortises the per-item claim, fence and counter work.
+int64_t item_tiles(int32_t cfg_tiles_per_item, int64_t tiles) {
+    if (cfg_tiles_per_item > 0) return cfg_tiles_per_item;
+    int64_t t = 16;
+    while (t < 128 && t * 128 < tiles) t *= 2;
+    return t;
+}
+
+int64_t block_bytes(int32_t mode, int32_t h, int32_t w) {
+    const int64_t plane = (int64_t)h * w;
+    return (mode == ADCT_SERVE_PLAIN ? 2 : 1) * Pool::round_up(plane) + 2 * plane;
+}
+
+// Hands an admitted request to the device (called with mu held).  Persistent
+// mode: publish its descriptor; plain mode: copy in, code, copy the SSE back
+// and record an event, all on the one stream.
 void issue(adct_server* S, int64_t k) {
     Req& r = S->reqs[(size_t)k];
-    char* base = S->pool_mem + r.off;
-    const int64_t plane = (int64_t)r.h * r.w;
-    char* src = base;
-    char* dst = base + Pool::round_up(plane);
-    char* q = dst + Pool::round_up(plane);
-    if (r.pitch == r.w)
-        hip_ok(S, hipMemcpyAsync(src, r.host, (size_t)plane, hipMemcpyHostToDevice, S->copy_stream));
-    else
-        hip_ok(S, hipMemcpy2DAsync(src, (size_t)r.w, r.host, (size_t)r.pitch, (size_t)r.w, (size_t)r.h,
-                                   hipMemcpyHostToDevice, S->copy_stream));
-    if (S->cfg.mode == ADCT_SERVE_PERSISTENT) {
-        ReqDesc& d = S->h_desc[k];
+    const Block b = block_of(S, r);
+    if (S->cfg.mode == ADCT_SERVE_PLAIN) {
+        if (r.pitch == r.w)
+            hip_ok(S, hipMemcpyAsync(b.src, r.host, (size_t)((int64_t)r.h * r.w), hipMemcpyHostToDevice, S->stream));
+        else
+            hip_ok(S, hipMemcpy2DAsync(b.src, (size_t)r.w, r.host, (size_t)r.pitch, (size_t)r.w, (size_t)r.h,
+                                       hipMemcpyHostToDevice, S->stream));
+        adct_plane ps{b.src, ADCT_U8, r.h, r.w, 0, r.w};
+        adct_plane pd{b.dst, ADCT_U8, r.h, r.w, 0, r.w};
+        int rc = adct_fwd2d_quant(&ps, S->cfg.qp, reinterpret_cast<int16_t*>(b.q), S->stream);
+        if (!rc)
+            rc = adct_dequant_recon(reinterpret_cast<int16_t*>(b.q), S->cfg.qp, &pd, &ps, r.h,
+                                    reinterpret_cast<int64_t*>(S->d_sse + k), S->stream);
+        if (rc && !S->hip_error) S->hip_error = rc;
+        hip_ok(S, hipMemcpyAsync(&S->h_comp[k].sse, S->d_sse + k, sizeof(int64_t), hipMemcpyDeviceToHost,
+                                 S->stream));
+        r.ev = S->free_events.back();
+        S->free_events.pop_back();
+        hip_ok(S, hipEventRecord(S->events[(size_t)r.ev], S->stream));
+    } else {
+        ReqDesc d;
         memset(&d, 0, sizeof d);
-        d.src = (uint64_t)(uintptr_t)src;
-        d.dst = (uint64_t)(uintptr_t)dst;
-        d.q = (uint64_t)(uintptr_t)q;
+        d.src = r.dev_src;
+        d.dst = (uint64_t)(uintptr_t)b.dst;
+        d.q = (uint64_t)(uintptr_t)b.q;
         d.height = (uint32_t)r.h;
         d.width = (uint32_t)r.w;
+        d.src_pitch = (uint32_t)r.pitch;
         d.nblk = (uint32_t)r.tiles;
-        d.tiles_per_item = (uint32_t)S->cfg.tiles_per_item;
-        d.nitems = (uint32_t)((r.tiles + S->cfg.tiles_per_item - 1) / S->cfg.tiles_per_item);
+        const int64_t tpi = item_tiles(S->cfg.tiles_per_item, r.tiles);
+        d.tiles_per_item = (uint32_t)tpi;
+        d.nitems = (uint32_t)((r.tiles + tpi - 1) / tpi);
         d.bw = (uint32_t)(r.w / 16);
         const FastDiv fb = make_fastdiv(d.bw), fi = make_fastdiv((uint32_t)(r.h / 16));
         d.bw_m = fb.m;
@@ -339,25 +444,21 @@ void issue(adct_server* S, int64_t k) {
         d.ipb_m = fi.m;
         d.ipb_s1 = fi.s1;
         d.ipb_s2 = fi.s2;
-        S->h_pubvals[k] = (uint32_t)(k + 1);
-        hip_ok(S, hipMemcpyAsync(S->d_desc + k, &d, sizeof d, hipMemcpyHostToDevice, S->copy_stream));
-        hip_ok(S, hipMemcpyAsync(st_published(S), S->h_pubvals + k, sizeof(uint32_t), hipMemcpyHostToDevice,
-                                 S->copy_stream));
-        if (loop_exited(S) && !S->stopping) launch_loop(S);
-    } else {
-        adct_plane ps{src, ADCT_U8, r.h, r.w, 0, r.w};
-        adct_plane pd{dst, ADCT_U8, r.h, r.w, 0, r.w};
-        int rc = adct_fwd2d_quant(&ps, S->cfg.qp, reinterpret_cast<int16_t*>(q), S->copy_stream);
-        if (!rc)
-            rc = adct_dequant_recon(reinterpret_cast<int16_t*>(q), S->cfg.qp, &pd, &ps, r.h,
-                                    reinterpret_cast<int64_t*>(S->d_sse + k), S->copy_stream);
-        if (rc && !S->hip_error) S->hip_error = rc;
-        hip_ok(S, hipMemcpyAsync(&S->h_comp[k].sse, S->d_sse + k, sizeof(int64_t), hipMemcpyDeviceToHost,
-                                 S->copy_stream));
-        r.ev = S->free_events.back();
-        S->free_events.pop_back();
-        hip_ok(S, hipEventRecord(S->events[(size_t)r.ev], S->copy_stream));
+        d.req = (uint32_t)k;
+        const int64_t slot = S->n_published++;
+        memcpy(&S->h_desc[slot], &d, sizeof d);
+        // the descriptor is written before the count that announces it
+        __atomic_store_n(S->h_count, (uint32_t)(slot + 1), __ATOMIC_RELEASE);
+        if (!S->stopping && loop_exited(S)) launch_loop(S);
     }
+    r.state = kRunning;
+    S->running.push_back(k);
+}
+
+bool event_done(adct_server* S, int ev) {
+    const hipError_t e = hipEventQuery(S->events[(size_t)ev]);
+    if (e != hipSuccess && e != hipErrorNotReady) hip_ok(S, e);
+    return e == hipSuccess;
 }
 
 void release_mem(adct_server* S, Req& r) {
@@ -368,33 +469,41 @@ void release_mem(adct_server* S, Req& r) {
     }
 }
 
+void finish(adct_server* S, int64_t k, int64_t now) {
+    Req& r = S->reqs[(size_t)k];
+    r.sse = __atomic_load_n(&S->h_comp[k].sse, __ATOMIC_ACQUIRE);
+    r.t_done = now;
+    r.state = kDone;
+    if (r.ev >= 0) {
+        S->free_events.push_back(r.ev);
+        r.ev = -1;
+    }
+    if (S->cfg.auto_release) {
+        release_mem(S, r);
+        r.state = kReleased;
+    }
+    ++S->n_done;
+}
+
 // Completions (called with mu held); returns whether any request finished.
-bool poll_done(adct_server* S, int64_t now) {
+bool poll_done(adct_server* S) {
     bool any = false;
+    if (S->cfg.mode == ADCT_SERVE_PLAIN) {
+        // one stream: requests complete in issue order
+        size_t i = 0;
+        while (i < S->running.size() && event_done(S, S->reqs[(size_t)S->running[i]].ev)) ++i;
+        if (i) {
+            const int64_t now = clock_ns();
+            for (size_t t = 0; t < i; ++t) finish(S, S->running[t], now);
+            S->running.erase(S->running.begin(), S->running.begin() + (ptrdiff_t)i);
+            any = true;
+        }
+        return any;
+    }
     for (size_t i = 0; i < S->running.size();) {
         const int64_t k = S->running[i];
-        Req& r = S->reqs[(size_t)k];
-        bool fin = false;
-        if (S->cfg.mode == ADCT_SERVE_PERSISTENT) {
-            fin = __atomic_load_n(&S->h_comp[k].flag, __ATOMIC_ACQUIRE) != 0;
-        } else {
-            const hipError_t e = hipEventQuery(S->events[(size_t)r.ev]);
-            fin = e == hipSuccess;
-            if (e != hipSuccess && e != hipErrorNotReady) hip_ok(S, e);
-        }
-        if (fin) {
-            r.sse = __atomic_load_n(&S->h_comp[k].sse, __ATOMIC_ACQUIRE);
-            r.t_done = now;
-            r.state = kDone;
-            if (r.ev >= 0) {
-                S->free_events.push_back(r.ev);
-                r.ev = -1;
-            }
-            if (S->cfg.auto_release) {
-                release_mem(S, r);
-                r.state = kReleased;
-            }
-            ++S->n_done;
+        if (__atomic_load_n(&S->h_comp[k].flag, __ATOMIC_ACQUIRE) != 0) {
+            finish(S, k, clock_ns());
             S->running[i] = S->running.back();
             S->running.pop_back();
             any = true;
@@ -406,6 +515,8 @@ bool poll_done(adct_server* S, int64_t now) {
 }
 
 void serve_thread(adct_server* S) {
+    // precise sleeps: the default timer slack would add tens of microseconds
+    (void)prctl(PR_SET_TIMERSLACK, 1UL, 0UL, 0UL, 0UL);
     (void)hipSetDevice(S->device);
     std::unique_lock<std::mutex> lk(S->mu);
     while (!S->quit) {
@@ -421,38 +532,43 @@ void serve_thread(adct_server* S) {
                 Req& r = S->reqs[(size_t)i];
                 r.off = off;
                 r.t_admit = now;
-                r.state = kRunning;
-                S->running.push_back(i);
                 issue(S, i);
                 ++admitted;
             });
-        const bool fin = poll_done(S, clock_ns());
         if (S->cfg.mode == ADCT_SERVE_PERSISTENT && !S->running.empty() && !S->stopping && loop_exited(S))
             launch_loop(S);  // the loop went idle and exited before this work was published
+        const bool fin = poll_done(S);
         if (fin) S->done_cv.notify_all();
-        if (!admitted && !fin) {
-            // nothing happened: wait for a submission, a release, or the next poll
-            int64_t wait_ns = S->running.empty() ? 200000 : 5000;
-            if (S->head < n && S->reqs[(size_t)S->head].state == kWaiting) {
-                const int64_t until = S->reqs[(size_t)S->head].t_arrival - now;
-                if (until > 0 && until < wait_ns) wait_ns = until;
-            }
-            S->cv.wait_for(lk, std::chrono::nanoseconds(wait_ns));
+        if (admitted || fin) continue;
+        // nothing happened: poll again soon while work is outstanding or about
+        // to arrive, otherwise sleep until a submission, a release or the
+        // next arrival
+        int64_t wait_ns = S->running.empty() ? 50000000 : 0;
+        if (S->head < n && S->reqs[(size_t)S->head].state == kWaiting && S->inflight < S->cfg.max_inflight) {
+            const int64_t until = S->reqs[(size_t)S->head].t_arrival - now;
+            if (until < wait_ns) wait_ns = until > 0 ? until : 0;
+        }
+        if (wait_ns <= kSpinWindowNs) {
+            lk.unlock();
+            for (int i = 0; i < 32; ++i) __builtin_ia32_pause();
+            lk.lock();
+        } else {
+            S->cv.wait_for(lk, std::chrono::nanoseconds(wait_ns - kSpinWindowNs / 2));
         }
     }
 }
 
 void free_server(adct_server* S) {
     if (S->loop_done) (void)hipEventDestroy(S->loop_done);
-    for (hipEvent_t e : S->events) (void)hipEventDestroy(e);
-    if (S->copy_stream) (void)hipStreamDestroy(S->copy_stream);
-    if (S->loop_stream) (void)hipStreamDestroy(S->loop_stream);
+    for (hipEvent_t e : S->events)
+        if (e) (void)hipEventDestroy(e);
+    if (S->stream) (void)hipStreamDestroy(S->stream);
     if (S->pool_mem) (void)hipFree(S->pool_mem);
     if (S->d_desc) (void)hipFree(S->d_desc);
     if (S->d_state) (void)hipFree(S->d_state);
     if (S->d_sse) (void)hipFree(S->d_sse);
     if (S->h_desc) (void)hipHostFree(S->h_desc);
-    if (S->h_pubvals) (void)hipHostFree(S->h_pubvals);
+    if (S->h_count) (void)hipHostFree(S->h_count);
     if (S->h_comp) (void)hipHostFree(S->h_comp);
     if (S->h_stop) (void)hipHostFree(S->h_stop);
     delete S->pool;
@@ -469,10 +585,9 @@ int adct_server_create(adct_server** out, const adct_server_cfg* cfg_in) {
     if (!out || !cfg_in) return ADCT_E_ARG;
     *out = nullptr;
     adct_server_cfg cfg = *cfg_in;
-    if (cfg.tiles_per_item == 0) cfg.tiles_per_item = 128;
     if (cfg.wgs_per_cu == 0) cfg.wgs_per_cu = 2;
-    if (cfg.idle_polls == 0) cfg.idle_polls = 1000000;
-    if (cfg.pool_bytes < 1024 || cfg.max_inflight < 1 || cfg.max_requests < 1 || cfg.tiles_per_item < 16 ||
+    if (cfg.idle_polls == 0) cfg.idle_polls = 100000;
+    if (cfg.pool_bytes < 1024 || cfg.max_inflight < 1 || cfg.max_requests < 1 || cfg.tiles_per_item < 0 ||
         cfg.tiles_per_item % 16 || cfg.wgs_per_cu < 1 || cfg.wgs_per_cu > 8 || cfg.idle_polls < 1 ||
         (cfg.mode != ADCT_SERVE_PERSISTENT && cfg.mode != ADCT_SERVE_PLAIN))
         return ADCT_E_ARG;
@@ -490,14 +605,20 @@ int adct_server_create(adct_server** out, const adct_server_cfg* cfg_in) {
     S->cus = prop.multiProcessorCount;
     S->pool = new Pool(cfg.pool_bytes);
     const size_t n = (size_t)cfg.max_requests;
+    const unsigned mapped = hipHostMallocMapped | hipHostMallocCoherent;
     bool ok = hipMalloc(reinterpret_cast<void**>(&S->pool_mem), (size_t)S->pool->capacity()) == hipSuccess &&
               hipMalloc(reinterpret_cast<void**>(&S->d_sse), n * sizeof(unsigned long long)) == hipSuccess &&
               hipMemset(S->d_sse, 0, n * sizeof(unsigned long long)) == hipSuccess &&
-              hipHostMalloc(reinterpret_cast<void**>(&S->h_comp), n * sizeof(Completion),
-                            hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess &&
-              hipHostMalloc(reinterpret_cast<void**>(&S->h_stop), 128, hipHostMallocMapped | hipHostMallocCoherent) ==
-                  hipSuccess &&
-              hipStreamCreateWithFlags(&S->copy_stream, hipStreamNonBlocking) == hipSuccess;
+              hipHostMalloc(reinterpret_cast<void**>(&S->h_comp), n * sizeof(Completion), mapped) == hipSuccess &&
+              hipHostMalloc(reinterpret_cast<void**>(&S->h_stop), 128, mapped) == hipSuccess &&
+              hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) == hipSuccess;
+    if (cfg.mode == ADCT_SERVE_PLAIN) {
+        S->events.resize((size_t)cfg.max_inflight, nullptr);
+        for (int i = 0; ok && i < cfg.max_inflight; ++i) {
+            ok = hipEventCreateWithFlags(&S->events[(size_t)i], hipEventDisableTiming) == hipSuccess;
+            S->free_events.push_back(i);
+        }
+    }
     if (ok) {
         memset(S->h_comp, 0, n * sizeof(Completion));
         *S->h_stop = 0;
@@ -505,21 +626,19 @@ int adct_server_create(adct_server** out, const adct_server_cfg* cfg_in) {
              hipHostGetDevicePointer(reinterpret_cast<void**>(&S->d_stop), S->h_stop, 0) == hipSuccess;
     }
     if (ok && cfg.mode == ADCT_SERVE_PERSISTENT) {
-        const size_t state_words = 64 + 2 * n;
+        const size_t state_words = 96 + 2 * n;
         ok = hipMalloc(reinterpret_cast<void**>(&S->d_desc), n * sizeof(ReqDesc)) == hipSuccess &&
              hipMalloc(reinterpret_cast<void**>(&S->d_state), state_words * sizeof(uint32_t)) == hipSuccess &&
              hipMemset(S->d_state, 0, state_words * sizeof(uint32_t)) == hipSuccess &&
-             hipHostMalloc(reinterpret_cast<void**>(&S->h_desc), n * sizeof(ReqDesc), 0) == hipSuccess &&
-             hipHostMalloc(reinterpret_cast<void**>(&S->h_pubvals), n * sizeof(uint32_t), 0) == hipSuccess &&
-             hipStreamCreateWithFlags(&S->loop_stream, hipStreamNonBlocking) == hipSuccess &&
-             hipEventCreateWithFlags(&S->loop_done, hipEventDisableTiming) == hipSuccess &&
-             hipDeviceSynchronize() == hipSuccess;
-    }
-    if (ok && cfg.mode == ADCT_SERVE_PLAIN) {
-        S->events.resize((size_t)cfg.max_inflight, nullptr);
-        for (int i = 0; ok && i < cfg.max_inflight; ++i) {
-            ok = hipEventCreateWithFlags(&S->events[(size_t)i], hipEventDisableTiming) == hipSuccess;
-            S->free_events.push_back(i);
+             hipHostMalloc(reinterpret_cast<void**>(&S->h_desc), n * sizeof(ReqDesc), mapped) == hipSuccess &&
+             hipHostMalloc(reinterpret_cast<void**>(&S->h_count), 128, mapped) == hipSuccess &&
+             hipEventCreateWithFlags(&S->loop_done, hipEventDisableTiming) == hipSuccess;
+        if (ok) {
+            memset(S->h_desc, 0, n * sizeof(ReqDesc));
+            *S->h_count = 0;
+            ok = hipHostGetDevicePointer(reinterpret_cast<void**>(&S->d_hdesc), S->h_desc, 0) == hipSuccess &&
+                 hipHostGetDevicePointer(reinterpret_cast<void**>(&S->d_hcount), S->h_count, 0) == hipSuccess &&
+                 hipDeviceSynchronize() == hipSuccess;
         }
     }
     if (!ok) {
@@ -542,9 +661,19 @@ int adct_server_submit(adct_server* S, const void* host_pixels, int32_t height, 
     r.h = height;
     r.w = width;
     r.pitch = pitch_bytes;
-    const int64_t plane = (int64_t)height * width;
-    r.bytes = 2 * Pool::round_up(plane) + 2 * plane;
-    r.tiles = plane / 256;
+    if (S->cfg.mode == ADCT_SERVE_PERSISTENT) {
+        // the loop reads the pixels in place: they must be in pinned host
+        // memory that the device can address, 16-byte aligned rows
+        if (((uintptr_t)host_pixels & 15) || (pitch_bytes & 15) || pitch_bytes > 0xffffffffll) return ADCT_E_ALIGN;
+        hipPointerAttribute_t attr;
+        memset(&attr, 0, sizeof attr);
+        const hipError_t e = hipPointerGetAttributes(&attr, host_pixels);
+        if (e != hipSuccess) (void)hipGetLastError();  // clear this thread's error state
+        if (e != hipSuccess || attr.type != hipMemoryTypeHost || !attr.devicePointer) return ADCT_E_ARG;
+        r.dev_src = (uint64_t)(uintptr_t)attr.devicePointer;
+    }
+    r.bytes = block_bytes(S->cfg.mode, height, width);
+    r.tiles = (int64_t)height * width / 256;
     r.t_arrival = arrival_ns < 0 ? clock_ns() : arrival_ns;
     std::lock_guard<std::mutex> lk(S->mu);
     if (S->stopping) return ADCT_E_STOPPED;
@@ -578,10 +707,9 @@ int adct_server_poll(adct_server* S, uint64_t ticket, adct_result* out) {
     out->sse = r.sse;
     out->t_done_ns = r.t_done;
     if (r.off >= 0) {
-        char* base = S->pool_mem + r.off;
-        const int64_t plane = (int64_t)r.h * r.w;
-        out->dst = base + Pool::round_up(plane);
-        out->q = base + 2 * Pool::round_up(plane);
+        const Block b = block_of(S, r);
+        out->dst = b.dst;
+        out->q = b.q;
     }
     return ADCT_OK;
 }
@@ -676,7 +804,7 @@ int adct_server_stop(adct_server* S, int32_t drain) {
     __atomic_store_n(S->h_stop, 1u, __ATOMIC_RELEASE);
     S->done_cv.notify_all();
     if (S->cfg.mode == ADCT_SERVE_PERSISTENT) {
-        // idle workgroups see the flag within a few polls
+        // the dispatcher sees the flag within a few polls and ends the launch
         const int64_t t0 = clock_ns();
         while (!loop_exited(S)) {
             if (clock_ns() - t0 > 20000000000ll) return ADCT_E_TIMEOUT;
@@ -698,7 +826,7 @@ int adct_server_destroy(adct_server* S) {
     }
     if (S->worker.joinable()) S->worker.join();
     if (rc == ADCT_E_TIMEOUT) return rc;  // the loop did not exit: keep its memory alive
-    (void)hipStreamSynchronize(S->copy_stream);
+    (void)hipStreamSynchronize(S->stream);
     free_server(S);
     return rc;
 }

@@ -191,3 +191,32 @@ def test_max_inflight_counts_held_results():
         srv.release(t)
     assert srv.stats()["completed"] == 6
     srv.close()
+
+
+def test_persistent_reads_pinned_memory_in_place_only():
+    srv = adct.Server(pool_bytes=1 << 26, qp=QP, max_requests=8)
+    pageable = np.zeros((64, 64), dtype=np.uint8)
+    with pytest.raises(adct.AdctError) as e:
+        srv.submit(pageable)
+    assert e.value.code == adct.E_ARG
+    pinned = torch.zeros((64, 80), dtype=torch.uint8).pin_memory()
+    with pytest.raises(adct.AdctError) as e:
+        srv.submit(pinned[:, 8:72])  # rows start 8 bytes into the buffer
+    assert e.value.code == adct.E_ALIGN
+    srv.close()
+
+
+def test_pitched_pinned_request_and_plain_pageable():
+    img = synth.ar1_image(28_000, 256, 320)
+    wide = torch.zeros((256, 384), dtype=torch.uint8).pin_memory()
+    wide[:, 16:336] = torch.from_numpy(img)
+    srv = adct.Server(pool_bytes=1 << 26, qp=QP, max_requests=8)
+    t = srv.submit(wide[:, 16:336])  # pitch 384 bytes, rows 16-byte aligned
+    srv.wait_all(30)
+    _check_all(srv, [t], [img], oracle_every=1)
+    srv.close()
+    plain = adct.Server(pool_bytes=1 << 26, qp=QP, mode=adct.SERVE_PLAIN, max_requests=8)
+    t = plain.submit(np.ascontiguousarray(img))  # pageable host memory is copied
+    plain.wait_all(30)
+    _check_all(plain, [t], [img])
+    plain.close()
