@@ -34,6 +34,18 @@ HBM_PEAK_GBS = 8000.0
 ENC_BYTES_PER_TILE = 256 + 1024 + 256     # u8 tile in, int32 coefficients out, u8 reconstruction out
 FWD_BYTES_PER_TILE = 256 + 1024           # two-kernel path: forward
 CPU_MIN_SECONDS = 10.0
+CPU_MAX_PASSES = 8
+COPY_PROBE_BYTES = 1 << 30
+
+# HBM traffic of the encoder launch, from rocprofv3 counter runs of
+# `python3 bench.py --steps 1 --warmup 0 --no-other --no-cpu-baseline`
+# (profiles/encode_zonal_traffic_1024x512x512_u8.md).  On gfx950 FETCH_SIZE
+# reads half, and WRITE_SIZE all, of the bytes that the same counters give
+# for the 1 GiB device copy of that run, hence the scale factors.  Valid
+# only for the kernel sources the counters were taken on.
+ENC_TRAFFIC = {"sources_sha256": "75b232b8438a6fb48a50170d6f89d31f09dbc21b3a6a97c658556178e42ba4d7",
+               "fetch_kib": 131303.3, "write_kib": 1311678.3, "fetch_scale": 2.0, "write_scale": 1.0}
+ENC_SOURCES = ("adct_butterfly.hpp", "adct_tile.hpp", "adct_core.hpp", "adct_plain.hip", "adct_internal.hpp")
 SERVE_TILES_PER_ITEM = 0     # persistent server: tiles per work item (0: chosen per request)
 SERVE_WGS_PER_CU = 2         # persistent server: loop workgroups per CU
 
@@ -54,6 +66,34 @@ def parse():
     ap.add_argument("--no-other", action="store_true", help="only the batched-image workload")
     ap.add_argument("--serve-requests", type=int, default=2000)
     return ap.parse_args()
+
+
+def encoder_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in ENC_SOURCES:
+        with open(os.path.join(ROOT, "paper_1606_07414_amd", "csrc", name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def encoder_traffic():
+    """Measured HBM bytes per encoder launch, or None when the kernel's
+    sources differ from those the counters were taken on."""
+    t = ENC_TRAFFIC
+    if t["sources_sha256"] is None or t["sources_sha256"] != encoder_sources_sha256():
+        return None
+    return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
+
+
+def copy_probe(torch, stream):
+    """Device-to-device copy of 1 GiB: achieved read + write GB/s (context
+    for the 8 TB/s peak, and the calibration kernel of the counter runs)."""
+    src = torch.ones(COPY_PROBE_BYTES, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    ms = timed(torch, lambda: dst.copy_(src), 10, stream)
+    del src, dst
+    return {"bytes_per_copy": 2 * COPY_PROBE_BYTES, "ms": ms, "gbs": 2 * COPY_PROBE_BYTES / (ms * 1e-3) / 1e9}
 
 
 def timed(torch, fn, reps, stream):
@@ -216,11 +256,11 @@ def serving(torch, adct, n_req, rates=(200, 500, 1000, 2000, 5000), warm=100):
 def cpu_baseline(img: np.ndarray):
     """The plain C oracle (dense int64 products, OpenMP over tiles): the whole
     workload (every image, every r), repeated until at least CPU_MIN_SECONDS
-    of host time (at most 3 passes)."""
+    of host time (at most CPU_MAX_PASSES passes)."""
     from tests import oracle_c
     H = img.shape[0]
     passes, t0 = 0, time.perf_counter()
-    while passes < 3 and (passes == 0 or time.perf_counter() - t0 < CPU_MIN_SECONDS):
+    while passes < CPU_MAX_PASSES and (passes == 0 or time.perf_counter() - t0 < CPU_MIN_SECONDS):
         for r in RS:
             coef = oracle_c.fwd2d_u8(img)
             oracle_c.zonal_recon_u8(coef, H, SIDE, r, img, SIDE)
@@ -300,6 +340,8 @@ def main():
         e2.synchronize()
         two[r] = (e0.elapsed_time(e1) / 5, e1.elapsed_time(e2) / 5)
     fwd_ms = float(np.mean([v[0] for v in two.values()]))
+    probe = copy_probe(torch, stream)
+    traffic = encoder_traffic()
 
     result = {
         "metric": "16x16 blocks/s (fwd+inv) and fraction of HBM peak",
@@ -319,8 +361,9 @@ def main():
                    "images": n_img, "side": SIDE, "zonal_r": list(RS)},
         "roofline": {"bound": "hbm", "kernel": "encode_zonal (k_group fwd + coef + zonal inverse + SSE)",
                      "achieved": enc_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": enc_gbs / HBM_PEAK_GBS,
-                     "traffic": None, "bytes_per_tile": ENC_BYTES_PER_TILE, "tiles_per_launch": ntiles,
-                     "avg_launch_ms": enc_avg_ms},
+                     "traffic": traffic, "bytes_per_tile": ENC_BYTES_PER_TILE, "tiles_per_launch": ntiles,
+                     "algorithmic_bytes_per_launch": ENC_BYTES_PER_TILE * ntiles, "avg_launch_ms": enc_avg_ms,
+                     "copy_probe_gbs": probe["gbs"]},
         "kernels_ms": {f"encode_zonal_r{r}": enc_ms[r] for r in RS},
         "two_kernel_path": {
             "fwd2d_ms": fwd_ms, "fwd2d_gbs": FWD_BYTES_PER_TILE * ntiles / (fwd_ms * 1e-3) / 1e9,
