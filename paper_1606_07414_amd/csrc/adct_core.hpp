@@ -84,6 +84,7 @@ struct GroupArgs {
     FastDiv bwdiv;           // division by bw
     FastDiv ipbdiv;          // division by tile rows per image (SSE image index)
     unsigned long long* sse; // per-image SSE accumulators
+    uint32_t image_tiles;    // tiles per image (launch geometry only)
 };
 
 // ---- sample rows as 16-bit pairs ------------------------------------------------
@@ -556,14 +557,23 @@ __device__ __forceinline__ void process_group(const GroupArgs& a, uint32_t g0, u
             // images adds per thread
             const uint32_t img0 = fdiv(fdiv(g0, a.bwdiv), a.ipbdiv);
             const uint32_t img1 = fdiv(fdiv(g0 + ntile - 1u, a.bwdiv), a.ipbdiv);
+            if (img0 != acc.img) {
+                sse_flush<TPW * 8>(acc, a.sse, red);
+                acc.s = 0;
+                acc.img = img0;
+            }
             if (img0 == img1) {
-                if (img0 != acc.img) {
-                    sse_flush<TPW * 8>(acc, a.sse, red);
-                    acc.s = 0;
-                    acc.img = img0;
-                }
                 acc.s += s;
+            } else if (img1 == img0 + 1u) {
+                // the group ends in the next image: close img0 with this
+                // group's part of it, then start img1 with the rest
+                const bool first = !rok || fdiv(rby, a.ipbdiv) == img0;
+                acc.s += first ? s : 0;
+                sse_flush<TPW * 8>(acc, a.sse, red);
+                acc.s = first ? 0 : s;
+                acc.img = img1;
             } else if (rok && s != 0) {
+                // images smaller than a group: one atomic per thread
                 atomicAdd(a.sse + fdiv(rby, a.ipbdiv), (unsigned long long)s);
             }
           }
@@ -582,16 +592,32 @@ namespace adct {
 constexpr int kTPW = ADCT_TPW;
 static_assert(kTPW >= 8 && (kTPW & (kTPW - 1)) == 0, "TPW must be a power of two >= 8");
 
-// One group per workgroup.
-// `gpw` consecutive groups per workgroup; the per-image SSE is reduced in
-// registers across them.
+#ifndef ADCT_SSE_SPREAD
+#define ADCT_SSE_SPREAD 256
+#endif
+// Workgroups of a launch that accumulates per-image SSE over large images
+// (more than kSseSpreadMin chunks per image) are dealt over the plane in
+// kSseSpread interleaved streams, so that the workgroups resident at one
+// time work on (and add to the SSE of) many different images instead of
+// queueing on the atomics of a few.
+constexpr uint32_t kSseSpread = ADCT_SSE_SPREAD;
+constexpr uint32_t kSseSpreadMin = 32;
+
+// `gpw` consecutive groups (a chunk) per workgroup; the per-image SSE is
+// reduced in registers across them.  spread_rows = 0: workgroup b takes
+// chunk b; otherwise the grid is kSseSpread x spread_rows and workgroup b
+// takes chunk (b % kSseSpread) * spread_rows + b / kSseSpread (workgroups
+// past the last chunk exit at once).
 template <int TPW, typename S, typename M>
-__global__ __launch_bounds__(TPW * 8) void k_group(GroupArgs a, uint32_t nblk, uint32_t gpw) {
+__global__ __launch_bounds__(TPW * 8) void k_group(GroupArgs a, uint32_t nblk, uint32_t gpw, uint32_t spread_rows) {
     __shared__ uint32_t lds[lds_words(TPW)];
     __shared__ long long red[TPW * 8 / 64];
     SseAcc acc{0, kNoImage};
     RowWords rows;
-    uint32_t g0 = blockIdx.x * gpw * (uint32_t)TPW;
+    const uint32_t chunk =
+        spread_rows ? (blockIdx.x % kSseSpread) * spread_rows + blockIdx.x / kSseSpread : blockIdx.x;
+    uint32_t g0 = chunk * gpw * (uint32_t)TPW;
+    if (g0 >= nblk) return;
     const uint32_t gend = min(nblk, g0 + gpw * (uint32_t)TPW);
     if constexpr (M::IN == kInSamples) load_group_rows<TPW, S>(a, g0, min((uint32_t)TPW, nblk - g0), rows);
     for (uint32_t k = 0; g0 < gend; ++k, g0 += (uint32_t)TPW) {

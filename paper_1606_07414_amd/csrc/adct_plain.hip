@@ -62,7 +62,12 @@ int launch_group(uint32_t nblk, hipStream_t s, const GroupArgs& a) {
     if (nblk == 0) return ADCT_OK;
     const uint32_t gpw = groups_per_wg(nblk);
     const uint32_t span = gpw * (uint32_t)kTPW;
-    hipLaunchKernelGGL((k_group<kTPW, S, M>), dim3((nblk + span - 1) / span), dim3(kTPW * 8), 0, s, a, nblk, gpw);
+    const uint32_t chunks = (nblk + span - 1) / span;
+    // launches that add to the SSE of large images interleave their chunks
+    const bool spread = M::SSE && a.sse && a.image_tiles / span > kSseSpreadMin;
+    const uint32_t rows = spread ? (chunks + kSseSpread - 1) / kSseSpread : 0u;
+    const uint32_t grid = rows ? rows * kSseSpread : chunks;
+    hipLaunchKernelGGL((k_group<kTPW, S, M>), dim3(grid), dim3(kTPW * 8), 0, s, a, nblk, gpw, rows);
     return launched();
 }
 
@@ -99,6 +104,7 @@ int prepare_sse(const adct_plane* dst, const adct_plane* ref, int32_t image_heig
                        reinterpret_cast<unsigned long long*>(sse), nimg);
     a.ref = plane_ref(ref ? ref : dst);
     a.ipbdiv = make_fastdiv((uint32_t)(image_height / 16));
+    a.image_tiles = (uint32_t)(image_height / 16) * (uint32_t)(dst->width / 16);
     a.sse = reinterpret_cast<unsigned long long*>(sse);
     return launched();
 }

@@ -356,3 +356,32 @@ def test_encoders_match_two_pass_paths():
     s3 = adct.encode_quant(x, 27, o1, image_height=128)
     s4 = adct.dequant_recon(q, 27, o2, ref=x, image_height=128)
     assert torch.equal(o1, o2) and torch.equal(s3, s4)
+
+
+# Per-image SSE over large images: the launch interleaves its workgroups over
+# the images, and groups that cross from one image into the next are split
+# between them (544 x 960 = 2040 tiles and 272 x 528 = 561 tiles per image,
+# neither a multiple of 16).
+@pytest.mark.parametrize("h,w,n", [(544, 960, 6), (272, 528, 8)])
+def test_sse_over_large_images_spread_and_split(h, w, n):
+    img = synth.ar1_batch(n, h, w, seed_base=950 + h)
+    x = dev(img)
+    out = torch.empty_like(x)
+    s = host(adct.encode_zonal(x, 8, out, image_height=h))
+    want = O.zonal_reconstruct(img, 8)
+    assert np.array_equal(host(out), want)
+    for i in range(n):
+        assert s[i] == O.sse(want[i * h:(i + 1) * h], img[i * h:(i + 1) * h]), i
+    res = np.concatenate([synth.laplacian_residual(960 + h + i, h, w) for i in range(n)])
+    xr = dev(res)
+    outr = torch.empty_like(xr)
+    s = host(adct.encode_quant(xr, 32, outr, image_height=h))
+    qw = O.quantise(O.fwd2d(res), 32)
+    want = O.from_tiles(O.round_clamp(O.reconstruct_fixed(O.dequantise(qw, 32)), -255, 255), *res.shape)
+    assert np.array_equal(host(outr), want)
+    for i in range(n):
+        assert s[i] == O.sse(want[i * h:(i + 1) * h], res[i * h:(i + 1) * h]), i
+    # the two-kernel path reaches the same sums
+    q = adct.fwd2d_quant(xr, 32)
+    s2 = host(adct.dequant_recon(q, 32, outr, ref=xr, image_height=h))
+    assert np.array_equal(s2, s)
