@@ -37,49 +37,85 @@ struct BatchArgs {
     uint32_t* heads;               // next unclaimed item of each sub-queue
 };
 
+// Claims an item for this workgroup from sub-queue q, moving on through the
+// following sub-queues while they are drained.  Returns false once every
+// sub-queue is.  Called with uniform control flow.
+__device__ __forceinline__ bool claim_item(const BatchArgs& b, uint32_t home, uint32_t& qi, uint32_t& q,
+                                           uint32_t& c, uint32_t* sh_claim) {
+    for (;;) {
+        __syncthreads();  // every thread has read the previous claim
+        if (threadIdx.x == 0) *sh_claim = atomicAdd(b.heads + q * kHeadStride, 1u);
+        __syncthreads();
+        c = __builtin_amdgcn_readfirstlane(*sh_claim);
+        if (c < b.qbeg[q + 1] - b.qbeg[q]) return true;
+        if (++qi >= kQueues) return false;
+        q = (home + qi) % kQueues;
+    }
+}
+
+// Items are software-pipelined: the claim of the next item is issued when an
+// item starts, resolved before its last group, and that group's prefetch
+// requests the first rows of the next item (possibly another image), so a
+// workgroup's memory stream does not stall between items.
+// `jobs` and `items` are read-only for the whole launch (restrict: their
+// loads are scalar and are not repeated after the kernel's own stores).
 template <int TPW, typename S, typename M>
-__global__ __launch_bounds__(TPW * 8) void k_batch(BatchArgs b) {
+__global__ __launch_bounds__(TPW * 8) void k_batch(BatchArgs b, const GroupArgs* __restrict__ jobs,
+                                                   const ItemDev* __restrict__ items) {
     __shared__ uint32_t lds[lds_words(TPW)];
     __shared__ long long red[TPW * 8 / 64];
-    __shared__ uint32_t claim;
+    __shared__ uint32_t sh_claim;
     const int tid = threadIdx.x;
     const uint32_t home = blockIdx.x % kQueues;
-    uint32_t qi = 0, q = home;
-    if (tid == 0) claim = atomicAdd(b.heads + q * kHeadStride, 1u);
-    __syncthreads();
+    uint32_t qi = 0, q = home, c = 0;
+    if (!claim_item(b, home, qi, q, c, &sh_claim)) return;
+    ItemDev item = items[b.qbeg[q] + c];
+    RowWords rows;
+    load_group_rows<TPW, S>(jobs[item.job], item.first, min((uint32_t)TPW, item.count), rows);
     for (;;) {
-        const uint32_t c = __builtin_amdgcn_readfirstlane(claim);
-        const uint32_t base = b.qbeg[q], cnt = b.qbeg[q + 1] - base;
-        if (c >= cnt) {
-            // sub-queue q is drained: move to the next one
-            if (++qi >= kQueues) break;
-            q = (home + qi) % kQueues;
-            __syncthreads();  // every thread has read `claim`
-            if (tid == 0) claim = atomicAdd(b.heads + q * kHeadStride, 1u);
-            __syncthreads();
-            continue;
-        }
-        // claim the next item now; the atomic's latency overlaps this item
+        // claim the next item of this sub-queue now; the atomic's latency
+        // overlaps this item's groups
         uint32_t next = 0;
         if (tid == 0) next = atomicAdd(b.heads + q * kHeadStride, 1u);
-        const ItemDev item = b.items[base + c];
-        const GroupArgs& a = b.jobs[item.job];
+        const GroupArgs a = jobs[item.job];
         const uint32_t gend = item.first + item.count;
         SseAcc acc{0, kNoImage};
-        RowWords rows;
-        uint32_t g0 = item.first;
-        load_group_rows<TPW, S>(a, g0, min((uint32_t)TPW, gend - g0), rows);
-        for (uint32_t k = 0; g0 < gend; ++k, g0 += (uint32_t)TPW) {
-            if (k) __syncthreads();
-            const uint32_t g0n = g0 + (uint32_t)TPW;
-            const uint32_t ntn = g0n < gend ? min((uint32_t)TPW, gend - g0n) : 0u;
-            process_group<TPW, S, M>(a, g0, min((uint32_t)TPW, gend - g0), lds, red, acc, rows, g0n, ntn, a.qs,
-                                     a.dqs);
+        bool have_next = false;
+        ItemDev nitem = item;
+        for (uint32_t g0 = item.first, k = 0; g0 < gend; g0 += (uint32_t)TPW, ++k) {
+            if (k) __syncthreads();  // the previous group's LDS reads are done
+            uint32_t g0n = g0 + (uint32_t)TPW;
+            uint32_t ntn = g0n < gend ? min((uint32_t)TPW, gend - g0n) : 0u;
+            if (g0n >= gend) {
+                // last group of the item: resolve the next claim, prefetch from it
+                __syncthreads();  // every thread has read the previous claim
+                if (tid == 0) sh_claim = next;
+                __syncthreads();
+                const uint32_t cn = __builtin_amdgcn_readfirstlane(sh_claim);
+                if (cn < b.qbeg[q + 1] - b.qbeg[q]) {
+                    nitem = items[b.qbeg[q] + cn];
+                    have_next = true;
+                    g0n = nitem.first;
+                    ntn = min((uint32_t)TPW, nitem.count);
+                }
+            }
+            // (the scale tables are read from the job array itself: indexed
+            // reads of a private copy would go through scratch)
+            process_group<TPW, S, M>(a, g0, min((uint32_t)TPW, gend - g0), lds, red, acc, rows, jobs[nitem.job],
+                                     g0n, ntn, jobs[item.job].qs, jobs[item.job].dqs);
         }
         if (a.sse) sse_flush<TPW * 8>(acc, a.sse, red);
-        __syncthreads();  // every thread has read `claim` and finished with LDS
-        if (tid == 0) claim = next;
-        __syncthreads();
+        if (have_next) {
+            item = nitem;
+            continue;
+        }
+        // sub-queue q is drained: the following ones, without prefetch
+        if (++qi >= kQueues) break;
+        q = (home + qi) % kQueues;
+        if (!claim_item(b, home, qi, q, c, &sh_claim)) break;
+        item = items[b.qbeg[q] + c];
+        __syncthreads();  // every thread is finished with LDS (sse_flush, last group)
+        load_group_rows<TPW, S>(jobs[item.job], item.first, min((uint32_t)TPW, item.count), rows);
     }
 }
 
@@ -97,7 +133,7 @@ int launched() { return hipGetLastError() == hipSuccess ? ADCT_OK : ADCT_E_HIP; 
 
 template <int TPW, typename S, typename M>
 void launch_k(unsigned grid, hipStream_t s, const BatchArgs& b) {
-    hipLaunchKernelGGL((k_batch<TPW, S, M>), dim3(grid), dim3(TPW * 8), 0, s, b);
+    hipLaunchKernelGGL((k_batch<TPW, S, M>), dim3(grid), dim3(TPW * 8), 0, s, b, b.jobs, b.items);
 }
 
 template <int TPW>

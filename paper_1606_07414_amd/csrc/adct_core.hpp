@@ -421,14 +421,16 @@ __device__ __forceinline__ void load_group_rows(const GroupArgs& a, uint32_t g0,
 }
 
 // `rows` holds this group's input rows (forward modes); once they are
-// consumed, the rows of the next group (g0n, ntn; ntn = 0 for none) are
+// consumed, the rows of the next group (tiles g0n .. g0n + ntn - 1 of the
+// plane of `an`, which may be another image's; ntn = 0 for none) are
 // requested into it, so their latency overlaps this group's remaining work.
 // `qs`, `dqs` must refer to kernel-argument or global memory: the per-class
 // selects in column_factors may be compiled into indexed loads.
 template <int TPW, typename S, typename M>
 __device__ __forceinline__ void process_group(const GroupArgs& a, uint32_t g0, uint32_t ntile,
                                               uint32_t* lds, long long* red, SseAcc& acc, RowWords& rows,
-                                              uint32_t g0n, uint32_t ntn, const Scale5& qs, const Scale5& dqs) {
+                                              const GroupArgs& an, uint32_t g0n, uint32_t ntn, const Scale5& qs,
+                                              const Scale5& dqs) {
     const int tid = threadIdx.x;
     const int rlt = tid % TPW, rip = tid / TPW;     // row role
     const int clt = tid >> 3, cp = tid & 7;         // column role
@@ -443,7 +445,7 @@ __device__ __forceinline__ void process_group(const GroupArgs& a, uint32_t g0, u
     // ---------------- input --------------------------------------------------
     if constexpr (M::IN == kInSamples) {
         fwd_rows<S>(rows, rlt, rip, lds, xk);
-        if (ntn) load_group_rows<TPW, S>(a, g0n, ntn, rows);
+        if (ntn) load_group_rows<TPW, S>(an, g0n, ntn, rows);
         __syncthreads();
         fwd_columns<S>(lds, clt, cp, ya, yb);
     } else {
@@ -624,7 +626,8 @@ __global__ __launch_bounds__(TPW * 8) void k_group(GroupArgs a, uint32_t nblk, u
         if (k) __syncthreads();  // the previous group's LDS reads are done
         const uint32_t g0n = g0 + (uint32_t)TPW;
         const uint32_t ntn = g0n < gend ? min((uint32_t)TPW, gend - g0n) : 0u;
-        process_group<TPW, S, M>(a, g0, min((uint32_t)TPW, nblk - g0), lds, red, acc, rows, g0n, ntn, a.qs, a.dqs);
+        process_group<TPW, S, M>(a, g0, min((uint32_t)TPW, nblk - g0), lds, red, acc, rows, a, g0n, ntn, a.qs,
+                                 a.dqs);
     }
     if constexpr (M::SSE) {
         if (a.sse) sse_flush<TPW * 8>(acc, a.sse, red);

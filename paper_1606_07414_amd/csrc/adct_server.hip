@@ -225,8 +225,8 @@ __global__ __launch_bounds__(kServeTPW * 8) void k_serve(ServeArgs s) {
             if (i) __syncthreads();
             const uint32_t g0n = g0 + (uint32_t)TPW;
             const uint32_t ntn = g0n < gend ? min((uint32_t)TPW, gend - g0n) : 0u;
-            process_group<TPW, uint8_t, ServeMode>(a, g0, min((uint32_t)TPW, gend - g0), lds, red, acc, rows, g0n,
-                                                  ntn, s.qs, s.dqs);
+            process_group<TPW, uint8_t, ServeMode>(a, g0, min((uint32_t)TPW, gend - g0), lds, red, acc, rows, a,
+                                                  g0n, ntn, s.qs, s.dqs);
         }
         sse_flush<TPW * 8>(acc, a.sse, red);
         __syncthreads();
