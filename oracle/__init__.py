@@ -18,6 +18,8 @@ beside it.
                  steps, quantisation, reconstruction, SSE/PSNR.
 ``metrics``      the exact DCT-II and the similarity / coding measures of
                  Section 2.3 (Table 2).
+``image_experiment``  zig-zag retention of the first r coefficients and the
+                 SSIM index (Section 3.1 as the paper runs it).
 ``c/``           the same plain dense definition of the 2D forward and
                  zonal inverse in C (OpenMP over tiles), used as the timed
                  CPU baseline.

@@ -89,3 +89,60 @@ def test_wrong_stage_block_is_caught(monkeypatch):
 def test_dropped_permutation_is_caught(monkeypatch):
     monkeypatch.setattr(O, "P1_CYCLES", ())
     assert _fails(P.test_factorisation_equals_T)
+
+
+# ---- zig-zag retention and SSIM (image_experiment) ----
+from oracle import image_experiment as E  # noqa: E402
+import tests.test_oracle_image_experiment as PE  # noqa: E402
+
+
+def test_zigzag_wrong_direction_is_caught(monkeypatch):
+    def bad_order(n=16):
+        order = []
+        for s in range(2 * n - 1):
+            us = range(max(0, s - n + 1), min(s, n - 1) + 1)
+            if s % 2 == 1:  # directions swapped
+                us = reversed(us)
+            order.extend((u, s - u) for u in us)
+        return order
+    monkeypatch.setattr(E, "zigzag_order", bad_order)
+    assert _fails(PE.test_8x8_order_is_the_jpeg_table)
+    assert _fails(PE.test_16x16_order_starts_as_jpeg)
+
+
+def test_zigzag_row_major_scan_is_caught(monkeypatch):
+    monkeypatch.setattr(E, "zigzag_order", lambda n=16: [(u, v) for u in range(n) for v in range(n)])
+    assert _fails(PE.test_order_is_a_scan, 16)
+
+
+def test_ssim_wrong_sigma_is_caught(monkeypatch):
+    def bad_window():
+        k = np.arange(11) - 5.0
+        g = np.exp(-(k[:, None] ** 2 + k[None, :] ** 2) / (2.0 * 1.0 ** 2))
+        return g / g.sum()
+    monkeypatch.setattr(E, "ssim_window", bad_window)
+    assert _fails(PE.test_window)
+
+
+def test_ssim_swapped_constants_are_caught(monkeypatch):
+    monkeypatch.setattr(E, "SSIM_K1", 0.03)
+    monkeypatch.setattr(E, "SSIM_K2", 0.01)
+    assert _fails(PE.test_ssim_constant_images_closed_form)
+    assert _fails(PE.test_ssim_scaled_image_closed_form)
+
+
+def test_ssim_covariance_without_mean_product_is_caught(monkeypatch):
+    real_local_mean = E._local_mean
+
+    def bad_map(a, b):
+        x, y = np.asarray(a, np.float64), np.asarray(b, np.float64)
+        w = E.ssim_window()
+        c1, c2 = (E.SSIM_K1 * E.SSIM_L) ** 2, (E.SSIM_K2 * E.SSIM_L) ** 2
+        mx, my = real_local_mean(x, w), real_local_mean(y, w)
+        sxx = real_local_mean(x * x, w) - mx * mx
+        syy = real_local_mean(y * y, w) - my * my
+        sxy = real_local_mean(x * y, w)  # dropped the mean product
+        return ((2 * mx * my + c1) * (2 * sxy + c2)) / ((mx * mx + my * my + c1) * (sxx + syy + c2))
+    monkeypatch.setattr(E, "ssim_map", bad_map)
+    assert _fails(PE.test_ssim_of_an_image_with_itself_is_one)
+    assert _fails(PE.test_ssim_brute_force_tiny)
