@@ -84,6 +84,11 @@ int adct_abi_version(void);
  * W[u*16+v] = 256 / (d_u d_v), d = diag(T T^T).  Any pointer may be NULL. */
 int adct_constants(int32_t* T256, double* s16, int32_t* W256);
 
+/* Host copy of the zig-zag ranks the kernels use (Section 3.1's retention
+ * order): rank256[u*16+v] = position of coefficient (u, v) in the scan
+ * (see adct_zigzag).  ADCT_E_ARG for NULL. */
+int adct_zigzag_ranks(int32_t* rank256);
+
 /* Host copies of the quantisation tables for `qp` (Section 2.1: S merged
  * into the quantiser).  Step Delta = 2^((qp-4)/6), qp in [0, 63].
  *   qs[u*16+v]  = fp32(s_u s_v / Delta)        (forward scale)
@@ -144,6 +149,15 @@ int adct_dequant(const int16_t* q, int64_t nblk, int qp, int32_t* zfix, void* st
  * coef, zfix: device int32 [nblk][16][16]. */
 int adct_zonal(const int32_t* coef, int64_t nblk, int r, int32_t* zfix, void* stream);
 
+/* Zig-zag retention of the first r coefficients of each block (Section 3.1:
+ * the experiment keeps the first r elements of the zig-zag sequence, r up to
+ * 150), S folded in as for adct_zonal: zfix = Y * W[u][v] where the rank of
+ * (u, v) in the scan is below r, 0 elsewhere.  The scan is the JPEG zig-zag
+ * extended to 16x16 (anti-diagonals u + v in turn, u rising on odd and
+ * falling on even ones).  r in [0, 256].  coef, zfix: device int32
+ * [nblk][16][16]. */
+int adct_zigzag(const int32_t* coef, int64_t nblk, int r, int32_t* zfix, void* stream);
+
 /* Reconstruction from 8-fractional-bit coefficients (Section 3.1 inverse):
  * R = T^T zfix T per block, sample = clamp(floor((R + 128) / 256)) to
  * [0, 255] (U8) or [-255, 255] (I16), written into the plane `dst`, whose
@@ -171,6 +185,12 @@ int adct_zonal_recon(const int32_t* coef, int r, const adct_plane* dst,
                      const adct_plane* ref, int32_t image_height, int64_t* sse,
                      void* stream);
 
+/* adct_zigzag followed by adct_recon (and the optional SSE, as above).  Only
+ * the block rows and columns that hold kept coefficients are read. */
+int adct_zigzag_recon(const int32_t* coef, int r, const adct_plane* dst,
+                      const adct_plane* ref, int32_t image_height, int64_t* sse,
+                      void* stream);
+
 /* adct_dequant followed by adct_recon (and the optional SSE, as above). */
 int adct_dequant_recon(const int16_t* q, int qp, const adct_plane* dst,
                        const adct_plane* ref, int32_t image_height, int64_t* sse,
@@ -187,6 +207,13 @@ int adct_dequant_recon(const int16_t* q, int qp, const adct_plane* dst,
 int adct_encode_zonal(const adct_plane* src, int r, int32_t* coef, const adct_plane* dst,
                       int32_t image_height, int64_t* sse, void* stream);
 
+/* Single-pass encoder with reconstruction, zig-zag form (Section 3.1's
+ * experiment as the paper runs it): as adct_encode_zonal with the first r
+ * coefficients of the zig-zag scan kept (adct_zigzag).  Bit-identical to
+ * adct_fwd2d + adct_zigzag_recon.  r in [0, 256]. */
+int adct_encode_zigzag(const adct_plane* src, int r, int32_t* coef, const adct_plane* dst,
+                       int32_t image_height, int64_t* sse, void* stream);
+
 /* Single-pass encoder with reconstruction, quantised form (Section 3.2's
  * use, S folded into the quantiser): levels q as adct_fwd2d_quant, stored to
  * `q` unless NULL, then dequantisation, inverse, rounding and clamping into
@@ -194,6 +221,20 @@ int adct_encode_zonal(const adct_plane* src, int r, int32_t* coef, const adct_pl
  * adct_fwd2d_quant + adct_dequant_recon. */
 int adct_encode_quant(const adct_plane* src, int qp, int16_t* q, const adct_plane* dst,
                       int32_t image_height, int64_t* sse, void* stream);
+
+/* ---- image quality ----------------------------------------------------- */
+
+/* Mean SSIM per image (the structural similarity index of Wang, Bovik,
+ * Sheikh and Simoncelli, 2004, reported beside PSNR in Section 3.1): local
+ * means, variances and covariance under an 11x11 Gaussian window of standard
+ * deviation 1.5 (unit sum), K1 = 0.01, K2 = 0.03, L = 255, evaluated at every
+ * position where the window lies inside the image, then averaged.  a, b:
+ * uint8 planes of the same shape (else ADCT_E_DTYPE / ADCT_E_SHAPE), images
+ * of `image_height` rows (a multiple of 16 dividing the height).
+ * ssim: device float64 [height / image_height], 8-byte aligned, overwritten.
+ * Computed in float64; the summation order over positions is not fixed, so
+ * repeated calls agree to about 1e-15 relative. */
+int adct_ssim(const adct_plane* a, const adct_plane* b, int32_t image_height, double* ssim, void* stream);
 
 /* ---- uneven batches: one persistent launch over a device work queue -- */
 /* Many images of different sizes coded by ONE launch: the host cuts every
@@ -207,8 +248,9 @@ int adct_encode_quant(const adct_plane* src, int qp, int16_t* q, const adct_plan
 typedef struct adct_job {
     adct_plane src;   /* input image, U8 or I16 (one type per batch)            */
     adct_plane dst;   /* reconstruction, same shape and type as src             */
-    void* coef;       /* ADCT_OP_ZONAL: int32 coefficients; ADCT_OP_QUANT: int16
-                         levels; block-major [nblk][16][16]; NULL: not stored    */
+    void* coef;       /* ADCT_OP_ZONAL, ADCT_OP_ZIGZAG: int32 coefficients;
+                         ADCT_OP_QUANT: int16 levels; block-major
+                         [nblk][16][16]; NULL: not stored                       */
     int64_t* sse;     /* device int64: exact SSE of dst against src, or NULL    */
 } adct_job;
 
@@ -221,8 +263,9 @@ typedef struct adct_tune {
     int32_t reserved;
 } adct_tune;
 
-#define ADCT_OP_ZONAL 1  /* param = r in [0, 16]  (adct_encode_zonal per image) */
-#define ADCT_OP_QUANT 2  /* param = qp in [0, 63] (adct_encode_quant per image) */
+#define ADCT_OP_ZONAL  1  /* param = r in [0, 16]  (adct_encode_zonal per image)  */
+#define ADCT_OP_QUANT  2  /* param = qp in [0, 63] (adct_encode_quant per image)  */
+#define ADCT_OP_ZIGZAG 3  /* param = r in [0, 256] (adct_encode_zigzag per image) */
 
 typedef struct adct_batch adct_batch;
 

@@ -45,7 +45,7 @@ class Tune(ctypes.Structure):
                 "wgs_per_cu": self.wgs_per_cu}
 
 
-OP_ZONAL, OP_QUANT = 1, 2
+OP_ZONAL, OP_QUANT, OP_ZIGZAG = 1, 2, 3
 SERVE_PERSISTENT, SERVE_PLAIN = 0, 1
 
 
@@ -92,6 +92,11 @@ _SIGNATURES = {
     "adct_quant": (ctypes.c_int, [_P, _I64, ctypes.c_int, _P, _P]),
     "adct_dequant": (ctypes.c_int, [_P, _I64, ctypes.c_int, _P, _P]),
     "adct_zonal": (ctypes.c_int, [_P, _I64, ctypes.c_int, _P, _P]),
+    "adct_zigzag": (ctypes.c_int, [_P, _I64, ctypes.c_int, _P, _P]),
+    "adct_zigzag_ranks": (ctypes.c_int, [_P]),
+    "adct_zigzag_recon": (ctypes.c_int, [_P, ctypes.c_int, _PP, _PP, _I32, _P, _P]),
+    "adct_encode_zigzag": (ctypes.c_int, [_PP, ctypes.c_int, _P, _PP, _I32, _P, _P]),
+    "adct_ssim": (ctypes.c_int, [_PP, _PP, _I32, _P, _P]),
     "adct_recon": (ctypes.c_int, [_P, _PP, _P]),
     "adct_sse": (ctypes.c_int, [_PP, _PP, _I32, _P, _P]),
     "adct_fwd2d_quant": (ctypes.c_int, [_PP, ctypes.c_int, _P, _P]),
@@ -224,6 +229,13 @@ def psnr(sse, pixels_per_image: float, peak: float = 255.0) -> np.ndarray:
     return out
 
 
+def zigzag_ranks() -> np.ndarray:
+    """16x16 int32: the scan position of every coefficient, as the kernels use it."""
+    r = np.empty(256, np.int32)
+    _check(_lib().adct_zigzag_ranks(r.ctypes.data), "zigzag_ranks")
+    return r.reshape(16, 16)
+
+
 def host_butterfly(x, inverse: bool = False) -> np.ndarray:
     x = np.ascontiguousarray(np.asarray(x, dtype=np.int32).reshape(16))
     y = np.empty(16, np.int32)
@@ -295,6 +307,15 @@ def zonal(coef, r: int, zfix=None, stream=None):
     return zfix
 
 
+def zigzag(coef, r: int, zfix=None, stream=None):
+    torch = _torch()
+    n = _blocks(coef, torch.int32, "zigzag")
+    if zfix is None:
+        zfix = _new_blocks(n, torch.int32, coef)
+    _check(_lib().adct_zigzag(coef.data_ptr(), n, r, zfix.data_ptr(), _stream(stream)), "zigzag")
+    return zfix
+
+
 def recon(zfix, dst, stream=None):
     p = plane(dst)
     _check(_lib().adct_recon(zfix.data_ptr(), ctypes.byref(p), _stream(stream)), "recon")
@@ -317,6 +338,14 @@ def zonal_recon(coef, r: int, dst, ref=None, image_height=None, sse=None, stream
     rp, ih, sse, sp = _ref_args(ref, image_height, sse, dst)
     _check(_lib().adct_zonal_recon(coef.data_ptr(), r, ctypes.byref(p), ctypes.byref(rp) if rp else None,
                                    ih, sp, _stream(stream)), "zonal_recon")
+    return sse
+
+
+def zigzag_recon(coef, r: int, dst, ref=None, image_height=None, sse=None, stream=None):
+    p = plane(dst)
+    rp, ih, sse, sp = _ref_args(ref, image_height, sse, dst)
+    _check(_lib().adct_zigzag_recon(coef.data_ptr(), r, ctypes.byref(p), ctypes.byref(rp) if rp else None,
+                                    ih, sp, _stream(stream)), "zigzag_recon")
     return sse
 
 
@@ -346,6 +375,28 @@ def encode_zonal(src, r: int, dst, coef=None, image_height=None, sse=None, want_
     _check(_lib().adct_encode_zonal(ctypes.byref(ps), r, coef.data_ptr() if coef is not None else None,
                                     ctypes.byref(pd), ih, sp, _stream(stream)), "encode_zonal")
     return sse
+
+
+def encode_zigzag(src, r: int, dst, coef=None, image_height=None, sse=None, want_sse=True, stream=None):
+    """Returns the per-image SSE tensor (or None when want_sse is False)."""
+    ps, pd = plane(src), plane(dst)
+    ih, sse, sp = _sse_out(src, image_height, sse, want_sse)
+    _check(_lib().adct_encode_zigzag(ctypes.byref(ps), r, coef.data_ptr() if coef is not None else None,
+                                     ctypes.byref(pd), ih, sp, _stream(stream)), "encode_zigzag")
+    return sse
+
+
+def ssim(a, b, image_height=None, out=None, stream=None):
+    """Mean SSIM per image of two uint8 planes (float64 device tensor)."""
+    torch = _torch()
+    if image_height is None:
+        image_height = a.shape[0]
+    if out is None:
+        out = torch.empty(a.shape[0] // image_height, dtype=torch.float64, device=a.device)
+    pa, pb = plane(a), plane(b)
+    _check(_lib().adct_ssim(ctypes.byref(pa), ctypes.byref(pb), image_height, out.data_ptr(), _stream(stream)),
+           "ssim")
+    return out
 
 
 def encode_quant(src, qp: int, dst, q=None, image_height=None, sse=None, want_sse=True, stream=None):

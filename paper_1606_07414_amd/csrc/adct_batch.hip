@@ -146,6 +146,14 @@ int launch_tpw(int dtype, int op, int param, unsigned grid, hipStream_t s, const
             launch_k<TPW, int16_t, M>(grid, s, b);
         return launched();
     }
+    if (op == ADCT_OP_ZIGZAG) {
+        using M = Mode<kInSamples, kStoreY, kMidZigzag, kOutSamples, -1, true>;
+        if (dtype == ADCT_U8)
+            launch_k<TPW, uint8_t, M>(grid, s, b);
+        else
+            launch_k<TPW, int16_t, M>(grid, s, b);
+        return launched();
+    }
     if (dtype == ADCT_U8) {
         switch (param) {
             case 2: launch_k<TPW, uint8_t, Mode<kInSamples, kStoreY, kMidZonal, kOutSamples, 2, true>>(grid, s, b); break;
@@ -192,6 +200,8 @@ int make_job_args(const adct_job* jobs, int32_t njobs, int32_t op, int32_t param
         if (!quant_scales(param, &qs, &dqs)) return ADCT_E_ARG;
     } else if (op == ADCT_OP_ZONAL) {
         if (param < 0 || param > 16) return ADCT_E_ARG;
+    } else if (op == ADCT_OP_ZIGZAG) {
+        if (param < 0 || param > 256) return ADCT_E_ARG;
     } else {
         return ADCT_E_ARG;
     }

@@ -33,6 +33,25 @@ __host__ __device__ constexpr int log2_norm(int k) {
     return (int)((kLog2NormPacked >> (2 * k)) & 3u) + 2;
 }
 
+// Rank of coefficient (u, v) (u vertical, v horizontal frequency) in the
+// zig-zag scan of a 16x16 block, the retention order of Section 3.1: the
+// JPEG scan extended to 16x16, anti-diagonal s = u + v after anti-diagonal,
+// u rising on odd s and falling on even s.
+__host__ __device__ constexpr int zigzag_rank(int u, int v) {
+    const int s = u + v;
+    const int base = s < 16 ? s * (s + 1) / 2 : 256 - (31 - s) * (32 - s) / 2;
+    const int lo = s < 16 ? 0 : s - 15, hi = s < 16 ? s : 15;
+    return base + ((s & 1) ? u - lo : hi - u);
+}
+
+// Rows (and columns) of a block that hold the first r zig-zag coefficients.
+__host__ __device__ constexpr int zigzag_extent(int r) {
+    if (r <= 0) return 0;
+    int s = 0;
+    while (s < 15 && (s + 1) * (s + 2) / 2 < r) ++s;  // first r ranks lie on diagonals 0..s
+    return s + 1;
+}
+
 // X = T x.
 template <typename V>
 __host__ __device__ __forceinline__ void fwd16(const V (&x)[16], V (&X)[16]) {

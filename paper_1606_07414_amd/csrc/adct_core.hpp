@@ -61,7 +61,7 @@ constexpr int lds_words(int tpw) { return tpw * kIntTile; }
 
 enum InKind { kInSamples = 0, kInY = 1, kInZfix = 2, kInQ = 3 };
 enum CStore { kStoreNone = 0, kStoreY = 1, kStoreQ = 2 };
-enum Mid { kMidNone = 0, kMidZonal = 1, kMidQuant = 2, kMidDequant = 3 };
+enum Mid { kMidNone = 0, kMidZonal = 1, kMidQuant = 2, kMidDequant = 3, kMidZigzag = 4 };
 enum OutKind { kOutNothing = 0, kOutSamples = 1, kOutBlocks = 2 };
 
 template <int IN_, int STORE_, int MID_, int OUT_, int ZR_, bool SSE_>
@@ -338,6 +338,17 @@ __device__ __forceinline__ void zonal_weights_cols(int p, int rr, int32_t (&a)[1
     }
 }
 
+// Zig-zag retention of the first r coefficients with the S weights.
+__device__ __forceinline__ void zigzag_weights_cols(int p, int r, int32_t (&a)[16], int32_t (&b)[16]) {
+    const int la = log2_norm(p), lb = log2_norm(p + 8);
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int su = 8 - log2_norm(u);
+        a[u] = zigzag_rank(u, p) < r ? (int32_t)((uint32_t)a[u] << (su - la)) : 0;
+        b[u] = zigzag_rank(u, p + 8) < r ? (int32_t)((uint32_t)b[u] << (su - lb)) : 0;
+    }
+}
+
 __device__ __forceinline__ void quant_cols(const Scale5& qs, int p, const int32_t (&a)[16], const int32_t (&b)[16],
                                            int32_t (&qa)[16], int32_t (&qb)[16]) {
     float fa[3], fb[3];
@@ -463,6 +474,9 @@ __device__ __forceinline__ void process_group(const GroupArgs& a, uint32_t g0, u
                 const int r = M::ZR >= 0 ? M::ZR : a.r;
                 rows = r;
                 cols4 = (r + 3) >> 2;
+            } else if constexpr (M::MID == kMidZigzag) {
+                rows = zigzag_extent(a.r);
+                cols4 = (rows + 3) >> 2;
             }
             global_blocks_to_lds<TPW>(static_cast<const int32_t*>(a.cin) + (int64_t)g0 * 256, tid, ntile,
                                       rows, cols4, lds);
@@ -504,6 +518,8 @@ __device__ __forceinline__ void process_group(const GroupArgs& a, uint32_t g0, u
         dequant_cols(dqs, cp, ya, yb);
     } else if constexpr (M::MID == kMidZonal) {
         zonal_weights_cols<M::ZR>(cp, a.r, ya, yb);
+    } else if constexpr (M::MID == kMidZigzag) {
+        zigzag_weights_cols(cp, a.r, ya, yb);
     }
 
     if constexpr (M::OUT == kOutNothing) return;

@@ -97,6 +97,13 @@ int adct_constants(int32_t* T256, double* s16, int32_t* W256) {
     return ADCT_OK;
 }
 
+int adct_zigzag_ranks(int32_t* rank256) {
+    if (!rank256) return ADCT_E_ARG;
+    for (int u = 0; u < 16; ++u)
+        for (int v = 0; v < 16; ++v) rank256[u * 16 + v] = zigzag_rank(u, v);
+    return ADCT_OK;
+}
+
 int adct_quant_tables(int qp, float* qs256, float* dqs256) {
     Scale5Host q, d;
     if (!quant_scales(qp, &q, &d)) return ADCT_E_ARG;

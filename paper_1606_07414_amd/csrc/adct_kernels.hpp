@@ -68,6 +68,22 @@ __global__ __launch_bounds__(256) void k_dequant(const short4* __restrict__ in, 
     }
 }
 
+__global__ __launch_bounds__(256) void k_zigzag(const int4* __restrict__ in, int4* __restrict__ out,
+                                                uint64_t n4, int r) {
+    for (uint64_t t = blockIdx.x * 256ull + threadIdx.x; t < n4; t += (uint64_t)gridDim.x * 256ull) {
+        int u, v0;
+        elem_uv(t, u, v0);
+        const int su = 8 - log2_norm(u);
+        const int4 y = in[t];
+        int4 o;
+        o.x = zigzag_rank(u, v0 + 0) < r ? (int32_t)((uint32_t)y.x << (su - log2_norm(v0 + 0))) : 0;
+        o.y = zigzag_rank(u, v0 + 1) < r ? (int32_t)((uint32_t)y.y << (su - log2_norm(v0 + 1))) : 0;
+        o.z = zigzag_rank(u, v0 + 2) < r ? (int32_t)((uint32_t)y.z << (su - log2_norm(v0 + 2))) : 0;
+        o.w = zigzag_rank(u, v0 + 3) < r ? (int32_t)((uint32_t)y.w << (su - log2_norm(v0 + 3))) : 0;
+        out[t] = o;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_zonal(const int4* __restrict__ in, int4* __restrict__ out,
                                                uint64_t n4, int r) {
     for (uint64_t t = blockIdx.x * 256ull + threadIdx.x; t < n4; t += (uint64_t)gridDim.x * 256ull) {

@@ -205,6 +205,17 @@ int adct_zonal(const int32_t* coef, int64_t nblk, int r, int32_t* zfix, void* st
     return launched();
 }
 
+int adct_zigzag(const int32_t* coef, int64_t nblk, int r, int32_t* zfix, void* stream) {
+    int rc;
+    if ((rc = check_blocks(coef, nblk)) || (rc = check_blocks(zfix, nblk))) return rc;
+    if (r < 0 || r > 256) return ADCT_E_ARG;
+    if (nblk == 0) return ADCT_OK;
+    const uint64_t n4 = (uint64_t)nblk * 64;
+    hipLaunchKernelGGL(k_zigzag, dim3(elem_grid(n4)), dim3(256), 0, static_cast<hipStream_t>(stream),
+                       reinterpret_cast<const int4*>(coef), reinterpret_cast<int4*>(zfix), n4, r);
+    return launched();
+}
+
 int adct_recon(const int32_t* zfix, const adct_plane* dst, void* stream) {
     int rc = check_plane(dst);
     if (rc) return rc;
@@ -234,6 +245,24 @@ int adct_zonal_recon(const int32_t* coef, int r, const adct_plane* dst, const ad
     if ((rc = prepare_sse(dst, ref, image_height, sse, s, a))) return rc;
     return sse ? launch_zonal<kInY, kStoreNone, true>(dst->dtype, r, (uint32_t)nblk, s, a)
                : launch_zonal<kInY, kStoreNone, false>(dst->dtype, r, (uint32_t)nblk, s, a);
+}
+
+int adct_zigzag_recon(const int32_t* coef, int r, const adct_plane* dst, const adct_plane* ref,
+                      int32_t image_height, int64_t* sse, void* stream) {
+    if (r < 0 || r > 256) return ADCT_E_ARG;
+    int rc = check_recon(dst, ref, image_height, sse);
+    if (rc) return rc;
+    const int64_t nblk = plane_blocks(dst);
+    if ((rc = check_blocks(coef, nblk))) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    GroupArgs a{};
+    a.cin = coef;
+    a.dst = plane_ref(dst);
+    set_geometry(dst, a);
+    a.r = r;
+    if ((rc = prepare_sse(dst, ref, image_height, sse, s, a))) return rc;
+    return sse ? launch_typed<Mode<kInY, kStoreNone, kMidZigzag, kOutSamples, -1, true>>(dst->dtype, (uint32_t)nblk, s, a)
+               : launch_typed<Mode<kInY, kStoreNone, kMidZigzag, kOutSamples, -1, false>>(dst->dtype, (uint32_t)nblk, s, a);
 }
 
 int adct_dequant_recon(const int16_t* q, int qp, const adct_plane* dst, const adct_plane* ref,
@@ -281,6 +310,35 @@ int adct_encode_zonal(const adct_plane* src, int r, int32_t* coef, const adct_pl
                    : launch_zonal<kInSamples, kStoreY, false>(src->dtype, r, n, s, a);
     return sse ? launch_zonal<kInSamples, kStoreNone, true>(src->dtype, r, n, s, a)
                : launch_zonal<kInSamples, kStoreNone, false>(src->dtype, r, n, s, a);
+}
+
+int adct_encode_zigzag(const adct_plane* src, int r, int32_t* coef, const adct_plane* dst,
+                       int32_t image_height, int64_t* sse, void* stream) {
+    if (r < 0 || r > 256) return ADCT_E_ARG;
+    int rc = check_plane(src);
+    if (rc) return rc;
+    if ((rc = check_plane(dst))) return rc;
+    if (!same_shape(src, dst)) return ADCT_E_SHAPE;
+    if (sse && (image_height <= 0 || (image_height & 15) || src->height % image_height)) return ADCT_E_SHAPE;
+    if (sse && ((uintptr_t)sse & 7)) return ADCT_E_ALIGN;
+    const int64_t nblk = plane_blocks(src);
+    if (coef && (rc = check_blocks(coef, nblk))) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    GroupArgs a{};
+    a.src = plane_ref(src);
+    set_geometry(src, a);
+    a.dst = plane_ref(dst);
+    set_geometry(dst, a);
+    a.cout = coef;
+    a.r = r;
+    if ((rc = prepare_sse(dst, src, image_height, sse, s, a))) return rc;
+    const uint32_t n = (uint32_t)nblk;
+    const int32_t dt = src->dtype;
+    if (coef)
+        return sse ? launch_typed<Mode<kInSamples, kStoreY, kMidZigzag, kOutSamples, -1, true>>(dt, n, s, a)
+                   : launch_typed<Mode<kInSamples, kStoreY, kMidZigzag, kOutSamples, -1, false>>(dt, n, s, a);
+    return sse ? launch_typed<Mode<kInSamples, kStoreNone, kMidZigzag, kOutSamples, -1, true>>(dt, n, s, a)
+               : launch_typed<Mode<kInSamples, kStoreNone, kMidZigzag, kOutSamples, -1, false>>(dt, n, s, a);
 }
 
 int adct_encode_quant(const adct_plane* src, int qp, int16_t* q, const adct_plane* dst, int32_t image_height,

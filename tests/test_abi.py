@@ -212,3 +212,31 @@ def test_default_tune_and_batch_arg_checks():
     assert lib.adct_batch_create(ctypes.byref(h), jobs, 1, adct.OP_ZONAL, 8, ctypes.byref(bad)) in (adct.E_ARG, adct.E_HIP)
     assert lib.adct_batch_submit(None, None) == adct.E_ARG
     assert lib.adct_batch_destroy(None) == adct.E_ARG
+
+
+# ---- zig-zag retention and SSIM (no GPU) ----
+def test_zigzag_ranks_match_oracle():
+    from oracle import image_experiment as E
+    assert np.array_equal(adct.zigzag_ranks(), E.zigzag_index())
+
+
+def test_zigzag_and_ssim_argument_checks():
+    lib = adct.lib()
+    p = _plane(FAKE, adct.U8, 32, 32, 32)
+    q = _plane(FAKE, adct.I16, 32, 32, 64)
+    assert lib.adct_zigzag(FAKE, 1, 257, FAKE, None) == adct.E_ARG
+    assert lib.adct_zigzag(FAKE, 1, -1, FAKE, None) == adct.E_ARG
+    assert lib.adct_zigzag(FAKE, 0, 150, FAKE, None) == adct.OK
+    assert lib.adct_zigzag_recon(FAKE, 300, ctypes.byref(p), None, 0, None, None) == adct.E_ARG
+    assert lib.adct_encode_zigzag(ctypes.byref(p), -2, None, ctypes.byref(p), 32, None, None) == adct.E_ARG
+    assert lib.adct_encode_zigzag(ctypes.byref(p), 10, None, ctypes.byref(q), 32, None, None) == adct.E_SHAPE
+    assert lib.adct_ssim(ctypes.byref(q), ctypes.byref(q), 32, FAKE, None) == adct.E_DTYPE
+    small = _plane(FAKE, adct.U8, 16, 32, 32)
+    assert lib.adct_ssim(ctypes.byref(p), ctypes.byref(small), 16, FAKE, None) == adct.E_SHAPE
+    assert lib.adct_ssim(ctypes.byref(p), ctypes.byref(p), 24, FAKE, None) == adct.E_SHAPE
+    assert lib.adct_ssim(ctypes.byref(p), ctypes.byref(p), 32, FAKE + 4, None) == adct.E_ALIGN
+    assert lib.adct_ssim(ctypes.byref(p), ctypes.byref(p), 32, None, None) == adct.E_ARG
+    h = ctypes.c_void_p()
+    jobs = (adct.Job * 1)()
+    jobs[0] = adct.Job(adct.Plane(FAKE, adct.U8, 16, 16, 0, 16), adct.Plane(FAKE, adct.U8, 16, 16, 0, 16), None, None)
+    assert lib.adct_batch_create(ctypes.byref(h), jobs, 1, adct.OP_ZIGZAG, 257, None) == adct.E_ARG
