@@ -11,9 +11,12 @@ SSE against the original.
 
 Printed: one JSON line with tiles/s (each tile counted once per r, i.e. per
 forward+inverse pair), the HIP-event-timed duration and roofline of the
-encoder kernel, the two-kernel path (adct_fwd2d + adct_zonal_recon) timed
-after the measured region for context, the CPU oracle on the same workload,
-and the PSNR per r.
+encoder kernel, the two-kernel path (adct_fwd2d + adct_zonal_recon) and a
+1 GiB device copy timed after the measured region for context, the CPU
+oracle on the same workload, and the PSNR per r.  Under `other_workloads`,
+after the measured region: the paper's zig-zag experiment with SSIM on the
+same images, one 256x256 image, 64 video residual frames, the uneven
+4096-image batch, and the serving comparison.
 """
 from __future__ import annotations
 
@@ -125,6 +128,33 @@ def single_image(torch, adct, stream):
            "inv2d_us": 1e3 * timed(torch, lambda: adct.inv2d(coef, stream=stream), 200, stream)}
     B = adct.scale(adct.fwd2d(x)).cpu().numpy().astype(np.float64)
     res["psnr_coef_vs_exact_dct_db"] = M.coefficient_psnr(B, M.exact_dct2d_tiles(O.to_tiles(img)))
+    return res
+
+
+ZIGZAG_R = (1, 3, 6, 10, 15, 21, 28, 36, 45, 55, 66, 78, 91, 105, 120, 136, 150)
+ADDITIONS = 44  # additions of one 16-point transform (Table 1)
+
+
+def image_experiment(torch, adct, stream, x, coef, out, n_img):
+    """Section 3.1's experiment as the paper runs it, on the batched images:
+    for each r, the single-pass encoder keeping the first r zig-zag
+    coefficients (coefficients, reconstruction, per-image SSE), and the SSIM
+    of every reconstruction; mean PSNR and SSIM, and both per additive cost."""
+    sse = torch.empty(n_img, dtype=torch.int64, device="cuda")
+    ss = torch.empty(n_img, dtype=torch.float64, device="cuda")
+    ntiles = x.numel() // 256
+    res = {"images": n_img, "tiles": ntiles, "additions": ADDITIONS, "bytes_per_tile": ENC_BYTES_PER_TILE, "r": {}}
+    for r in ZIGZAG_R:
+        ms_enc = timed(torch, lambda: adct.encode_zigzag(x, r, out, coef=coef, image_height=SIDE, sse=sse,
+                                                         stream=stream), 5, stream)
+        ms_ssim = timed(torch, lambda: adct.ssim(x, out, image_height=SIDE, out=ss, stream=stream), 3, stream)
+        p = float(np.mean(adct.psnr(sse.cpu().numpy(), SIDE * SIDE)))
+        m = float(ss.mean().item())
+        gbs = ENC_BYTES_PER_TILE * ntiles / (ms_enc * 1e-3) / 1e9
+        res["r"][r] = {"psnr_db": p, "ssim": m, "psnr_per_addition": p / ADDITIONS, "ssim_per_addition": m / ADDITIONS,
+                       "encoder_ms": ms_enc, "encoder_tiles_per_s": ntiles / (ms_enc * 1e-3), "encoder_gbs": gbs,
+                       "encoder_frac_of_8tbs": gbs / HBM_PEAK_GBS, "ssim_ms": ms_ssim,
+                       "ssim_images_per_s": n_img / (ms_ssim * 1e-3)}
     return res
 
 
@@ -373,9 +403,13 @@ def main():
         "input_gen_s": gen_s,
     }
     if not args.no_other:
+        t0 = time.perf_counter()
+        zz = image_experiment(torch, adct, stream, x, coef, out, n_img)
+        zz["wall_s"] = time.perf_counter() - t0
+        print(f"[bench] image_experiment_zigzag done in {zz['wall_s']:.1f} s", file=sys.stderr, flush=True)
         del coef, out, sse
         torch.cuda.empty_cache()
-        other = {}
+        other = {"image_experiment_zigzag_1024x512x512": zz}
         for name, fn in (("single_image_256x256", lambda: single_image(torch, adct, stream)),
                          ("video_residuals_64x1920x1088", lambda: video(torch, adct, stream)),
                          ("uneven_batch_4096", lambda: uneven_batch(torch, adct, stream)),

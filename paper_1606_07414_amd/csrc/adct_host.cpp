@@ -127,9 +127,11 @@ int adct_psnr(const int64_t* sse, int32_t n, double pixels_per_image, double pea
 
 int adct_default_tune(adct_tune* out) {
     if (!out) return ADCT_E_ARG;
-    out->tiles_per_group = 16;
-    out->groups_per_item = 4;
-    out->wgs_per_cu = 8;
+    // 32-tile groups, 64-tile items, 4 resident workgroups of 256 threads per
+    // CU: the fastest measured shape on uneven and uniform batches alike
+    out->tiles_per_group = 32;
+    out->groups_per_item = 2;
+    out->wgs_per_cu = 4;
     out->reserved = 0;
     return ADCT_OK;
 }
