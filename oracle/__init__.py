@@ -20,6 +20,8 @@ beside it.
                  Section 2.3 (Table 2).
 ``image_experiment``  zig-zag retention of the first r coefficients and the
                  SSIM index (Section 3.1 as the paper runs it).
+``t8``           the 8-point approximation T8 that T is built from, and its
+                 8x8 blockwise codec (Section 3.2's second scenario).
 ``c/``           the same plain dense definition of the 2D forward and
                  zonal inverse in C (OpenMP over tiles), used as the timed
                  CPU baseline.

@@ -146,3 +146,29 @@ def test_ssim_covariance_without_mean_product_is_caught(monkeypatch):
     monkeypatch.setattr(E, "ssim_map", bad_map)
     assert _fails(PE.test_ssim_of_an_image_with_itself_is_one)
     assert _fails(PE.test_ssim_brute_force_tiny)
+
+
+# ---- 8-point oracle (t8) ----
+from oracle import t8 as E8  # noqa: E402
+import tests.test_oracle_t8 as P8  # noqa: E402
+
+
+def test_t8_taken_from_odd_rows_is_caught(monkeypatch):
+    monkeypatch.setattr(E8, "transform_matrix_8", lambda: O.transform_matrix()[1::2, :8].copy())
+    assert _fails(P8.test_even_rows_of_T_are_symmetric_and_form_T8)
+    assert _fails(P8.test_factorisation_even_path_is_T8_with_14_additions)
+
+
+def test_t8_wrong_weight_is_caught(monkeypatch):
+    W = E8.zonal_weights_8()
+    bad = W.copy()
+    bad[1, 2] *= 2
+    monkeypatch.setattr(E8, "zonal_weights_8", lambda: bad.copy())
+    assert _fails(P8.test_weighted_roundtrip_is_64X)
+    assert _fails(P8.test_zonal8_special_cases)
+
+
+def test_t8_wrong_rounding_offset_is_caught(monkeypatch):
+    monkeypatch.setattr(E8, "round_clamp8",
+                        lambda R, lo, hi: np.clip(np.floor_divide(np.asarray(R, np.int64), 64), lo, hi))
+    assert _fails(P8.test_zonal8_special_cases)
