@@ -161,7 +161,8 @@ def image_experiment(torch, adct, stream, x, coef, out, n_img):
 def video(torch, adct, stream, frames=64):
     """64 residual frames of 1920x1088 4:2:0 (Laplacian, scale 8): per QP the
     single-pass encoder (levels + reconstruction + per-frame SSE) and the
-    two-kernel path, over all three planes."""
+    two-kernel path, over all three planes; and the same frames coded with
+    the 8-point transform on 8x8 blocks."""
     import synth
     planes = [[], [], []]
     for f in range(frames):
@@ -173,7 +174,8 @@ def video(torch, adct, stream, frames=64):
     outs = [torch.empty_like(x) for x in xs]
     qs = [torch.empty((x.numel() // 256, 16, 16), dtype=torch.int16, device="cuda") for x in xs]
     sses = [torch.empty(frames, dtype=torch.int64, device="cuda") for _ in xs]
-    res = {"frames": frames, "tiles": tiles, "bytes_per_tile_fused": 1536, "qp": {}}
+    q8s = [torch.empty((x.numel() // 64, 8, 8), dtype=torch.int16, device="cuda") for x in xs]
+    res = {"frames": frames, "tiles": tiles, "bytes_per_tile_fused": 1536, "bytes_per_block8_fused": 384, "qp": {}}
     for qp in (22, 27, 32, 37):
         def fused():
             for x, o, q, s, h in zip(xs, outs, qs, sses, heights):
@@ -194,6 +196,20 @@ def video(torch, adct, stream, frames=64):
                          "two_kernel_ms": ms_t, "two_kernel_tiles_per_s": tiles / (ms_t * 1e-3),
                          "psnr_y_u_v_db": [float(np.mean(p)) for p in psnr],
                          "psnr_yuv_6_1_1_db": float(np.mean((6 * psnr[0] + psnr[1] + psnr[2]) / 8))}
+        # the same frames with the 8-point transform on 8x8 blocks (Section 3.2's
+        # second scenario codes with both sizes): levels, reconstruction, SSE
+        def fused8():
+            for x, o, q8, s, h in zip(xs, outs, q8s, sses, heights):
+                adct.t8_encode_quant(x, qp, o, q=q8, image_height=h, sse=s, stream=stream)
+
+        ms8 = timed(torch, fused8, 10, stream)
+        fused8()
+        sse8 = [s.cpu().numpy().astype(np.float64) for s in sses]
+        psnr8 = [10 * np.log10(255.0 ** 2 * n / np.maximum(e, 1)) for e, n in zip(sse8, npix)]
+        res["qp"][qp]["t8"] = {"ms": ms8, "blocks8_per_s": 4 * tiles / (ms8 * 1e-3),
+                               "gbs": 384 * 4 * tiles / (ms8 * 1e-3) / 1e9,
+                               "psnr_yuv_6_1_1_db": float(np.mean((6 * psnr8[0] + psnr8[1] + psnr8[2]) / 8))}
+    res["additions_per_sample_2d"] = {"t16": 2 * 44 / 16, "t8": 2 * 14 / 8}
     return res
 
 

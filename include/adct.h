@@ -222,6 +222,48 @@ int adct_encode_zigzag(const adct_plane* src, int r, int32_t* coef, const adct_p
 int adct_encode_quant(const adct_plane* src, int qp, int16_t* q, const adct_plane* dst,
                       int32_t image_height, int64_t* sse, void* stream);
 
+/* ---- the 8-point transform T8 on 8x8 blocks ---------------------------- */
+/* T is built from two instances of the 8-point approximation T8 (Section
+ * 2.1); the instance on the sum path of the factorisation (Section 2.2) is
+ * T8[k][j] = T[2k][j], j < 8 (the even rows of T act on x_j + x_{15-j}
+ * only), computed with 14 additions.  Section 3.2's second scenario codes
+ * with both the 8- and the 16-point transform; these calls are the 8-point
+ * codec on disjoint 8x8 blocks, with S8 = diag(T8 T8^T)^(-1/2) folded in as
+ * for the 16-point calls: zonal weights W8 = 64 / (d_u d_v), quantiser
+ * tables qs = fp32(s_u s_v / Delta) and dqs = fp32(64 Delta s_u s_v), and
+ * reconstruction clamp(floor((R + 32) / 64)).  Planes: sides multiples of 8
+ * (else ADCT_E_SHAPE); sample (0,0) and the pitch aligned to 8 bytes for
+ * U8 and 16 bytes for I16 (else ADCT_E_ALIGN); coefficient arrays
+ * are block-major [nblk8][8][8] with block k = by * (width/8) + bx,
+ * element u*8 + v, 16-byte aligned.  image_height: a multiple of 8. */
+
+/* Host copies of T8 (row-major), the diagonal of S8 and W8. */
+int adct_t8_constants(int32_t* T64, double* s8, int32_t* W64);
+
+/* Host copies of the 8-point quantisation tables for `qp` in [0, 63]. */
+int adct_t8_quant_tables(int qp, float* qs64, float* dqs64);
+
+/* Y = T8 A T8^T for every 8x8 block A of src (U8 or I16); coef: device
+ * int32 [nblk8][8][8]. */
+int adct_t8_fwd2d(const adct_plane* src, int32_t* coef, void* stream);
+
+/* T8^T Y T8 for every block (block-major int32 in and out). */
+int adct_t8_inv2d(const int32_t* coef, int64_t nblk, int32_t* out, void* stream);
+
+/* Single-pass 8x8 encoder with reconstruction, zonal form: Y stored to coef
+ * unless NULL, the top-left r x r coefficients kept with S8 folded in
+ * (r in [0, 8]), inverse, rounding and clamping into dst ([0, 255] for U8,
+ * [-255, 255] for I16), and the exact per-image SSE when sse is non-NULL. */
+int adct_t8_encode_zonal(const adct_plane* src, int r, int32_t* coef, const adct_plane* dst,
+                         int32_t image_height, int64_t* sse, void* stream);
+
+/* Single-pass 8x8 encoder, quantised form: levels q = round(fp32(Y) * qs)
+ * (half away from zero, saturated to int16) stored unless NULL, then
+ * dequantisation to 6 fractional bits, inverse, rounding, clamping and the
+ * optional SSE. */
+int adct_t8_encode_quant(const adct_plane* src, int qp, int16_t* q, const adct_plane* dst,
+                         int32_t image_height, int64_t* sse, void* stream);
+
 /* ---- image quality ----------------------------------------------------- */
 
 /* Mean SSIM per image (the structural similarity index of Wang, Bovik,

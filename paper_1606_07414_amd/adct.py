@@ -97,6 +97,12 @@ _SIGNATURES = {
     "adct_zigzag_recon": (ctypes.c_int, [_P, ctypes.c_int, _PP, _PP, _I32, _P, _P]),
     "adct_encode_zigzag": (ctypes.c_int, [_PP, ctypes.c_int, _P, _PP, _I32, _P, _P]),
     "adct_ssim": (ctypes.c_int, [_PP, _PP, _I32, _P, _P]),
+    "adct_t8_constants": (ctypes.c_int, [_P, _P, _P]),
+    "adct_t8_quant_tables": (ctypes.c_int, [ctypes.c_int, _P, _P]),
+    "adct_t8_fwd2d": (ctypes.c_int, [_PP, _P, _P]),
+    "adct_t8_inv2d": (ctypes.c_int, [_P, _I64, _P, _P]),
+    "adct_t8_encode_zonal": (ctypes.c_int, [_PP, ctypes.c_int, _P, _PP, _I32, _P, _P]),
+    "adct_t8_encode_quant": (ctypes.c_int, [_PP, ctypes.c_int, _P, _PP, _I32, _P, _P]),
     "adct_recon": (ctypes.c_int, [_P, _PP, _P]),
     "adct_sse": (ctypes.c_int, [_PP, _PP, _I32, _P, _P]),
     "adct_fwd2d_quant": (ctypes.c_int, [_PP, ctypes.c_int, _P, _P]),
@@ -383,6 +389,61 @@ def encode_zigzag(src, r: int, dst, coef=None, image_height=None, sse=None, want
     ih, sse, sp = _sse_out(src, image_height, sse, want_sse)
     _check(_lib().adct_encode_zigzag(ctypes.byref(ps), r, coef.data_ptr() if coef is not None else None,
                                      ctypes.byref(pd), ih, sp, _stream(stream)), "encode_zigzag")
+    return sse
+
+
+# ---------------------------------------------------------------- 8-point calls
+def t8_constants():
+    """(T8 int32 8x8, s8 float64 [8], W8 int32 8x8)."""
+    T = np.empty(64, np.int32)
+    s = np.empty(8, np.float64)
+    W = np.empty(64, np.int32)
+    _check(_lib().adct_t8_constants(T.ctypes.data, s.ctypes.data, W.ctypes.data), "t8_constants")
+    return T.reshape(8, 8), s, W.reshape(8, 8)
+
+
+def t8_quant_tables(qp: int):
+    qs = np.empty(64, np.float32)
+    dqs = np.empty(64, np.float32)
+    _check(_lib().adct_t8_quant_tables(qp, qs.ctypes.data, dqs.ctypes.data), "t8_quant_tables")
+    return qs.reshape(8, 8), dqs.reshape(8, 8)
+
+
+def _nblk8(src):
+    return (src.shape[0] // 8) * (src.shape[1] // 8)
+
+
+def t8_fwd2d(src, coef=None, stream=None):
+    torch = _torch()
+    if coef is None:
+        coef = torch.empty((_nblk8(src), 8, 8), dtype=torch.int32, device=src.device)
+    p = plane(src)
+    _check(_lib().adct_t8_fwd2d(ctypes.byref(p), coef.data_ptr(), _stream(stream)), "t8_fwd2d")
+    return coef
+
+
+def t8_inv2d(coef, out=None, stream=None):
+    torch = _torch()
+    n = coef.numel() // 64
+    if out is None:
+        out = torch.empty_like(coef)
+    _check(_lib().adct_t8_inv2d(coef.data_ptr(), n, out.data_ptr(), _stream(stream)), "t8_inv2d")
+    return out
+
+
+def t8_encode_zonal(src, r: int, dst, coef=None, image_height=None, sse=None, want_sse=True, stream=None):
+    ps, pd = plane(src), plane(dst)
+    ih, sse, sp = _sse_out(src, image_height, sse, want_sse)
+    _check(_lib().adct_t8_encode_zonal(ctypes.byref(ps), r, coef.data_ptr() if coef is not None else None,
+                                       ctypes.byref(pd), ih, sp, _stream(stream)), "t8_encode_zonal")
+    return sse
+
+
+def t8_encode_quant(src, qp: int, dst, q=None, image_height=None, sse=None, want_sse=True, stream=None):
+    ps, pd = plane(src), plane(dst)
+    ih, sse, sp = _sse_out(src, image_height, sse, want_sse)
+    _check(_lib().adct_t8_encode_quant(ctypes.byref(ps), qp, q.data_ptr() if q is not None else None,
+                                       ctypes.byref(pd), ih, sp, _stream(stream)), "t8_encode_quant")
     return sse
 
 

@@ -10,7 +10,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libadct.so")
 
-SOURCES = ["adct_host.cpp", "adct_plain.hip", "adct_batch.hip", "adct_server.hip", "adct_metrics.hip"]
+SOURCES = ["adct_host.cpp", "adct_plain.hip", "adct_batch.hip", "adct_server.hip", "adct_metrics.hip",
+           "adct_t8.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

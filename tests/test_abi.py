@@ -240,3 +240,37 @@ def test_zigzag_and_ssim_argument_checks():
     jobs = (adct.Job * 1)()
     jobs[0] = adct.Job(adct.Plane(FAKE, adct.U8, 16, 16, 0, 16), adct.Plane(FAKE, adct.U8, 16, 16, 0, 16), None, None)
     assert lib.adct_batch_create(ctypes.byref(h), jobs, 1, adct.OP_ZIGZAG, 257, None) == adct.E_ARG
+
+
+# ---- 8-point calls (no GPU) ----
+def test_t8_constants_and_tables_match_oracle():
+    from oracle import t8 as E8
+    T, s, W = adct.t8_constants()
+    assert np.array_equal(T, E8.transform_matrix_8())
+    assert np.array_equal(s, E8.scaling_vector_8())
+    assert np.array_equal(W, E8.zonal_weights_8())
+    for qp in range(64):
+        qs, dqs = adct.t8_quant_tables(qp)
+        oqs, odqs = E8.quant_tables_8(qp)
+        assert np.array_equal(qs.view(np.uint32), oqs.view(np.uint32)), qp
+        assert np.array_equal(dqs.view(np.uint32), odqs.view(np.uint32)), qp
+
+
+def test_t8_argument_checks():
+    lib = adct.lib()
+    p = _plane(FAKE, adct.U8, 24, 40, 48)
+    odd = _plane(FAKE, adct.U8, 20, 40, 48)
+    assert lib.adct_t8_fwd2d(ctypes.byref(odd), FAKE, None) == adct.E_SHAPE
+    assert lib.adct_t8_fwd2d(ctypes.byref(p), FAKE + 8, None) == adct.E_ALIGN
+    assert lib.adct_t8_fwd2d(ctypes.byref(p), None, None) == adct.E_ARG
+    assert lib.adct_t8_encode_zonal(ctypes.byref(p), 9, None, ctypes.byref(p), 24, None, None) == adct.E_ARG
+    assert lib.adct_t8_encode_zonal(ctypes.byref(p), 4, None, ctypes.byref(p), 12, FAKE, None) == adct.E_SHAPE
+    assert lib.adct_t8_encode_quant(ctypes.byref(p), 64, None, ctypes.byref(p), 24, None, None) == adct.E_ARG
+    assert lib.adct_t8_inv2d(FAKE, -1, FAKE, None) == adct.E_ARG
+    assert lib.adct_t8_inv2d(FAKE, 0, FAKE, None) == adct.OK
+    # u8 rows need 8-byte alignment, int16 rows 16
+    assert lib.adct_t8_fwd2d(ctypes.byref(_plane(FAKE + 8, adct.U8, 8, 8, 8)), None, None) == adct.E_ARG
+    assert lib.adct_t8_fwd2d(ctypes.byref(_plane(FAKE + 4, adct.U8, 8, 8, 8)), FAKE, None) == adct.E_ALIGN
+    assert lib.adct_t8_fwd2d(ctypes.byref(_plane(FAKE + 8, adct.I16, 8, 8, 16)), FAKE, None) == adct.E_ALIGN
+    assert lib.adct_t8_fwd2d(ctypes.byref(_plane(FAKE, adct.I16, 8, 8, 24)), FAKE, None) == adct.E_ALIGN
+    assert lib.adct_t8_quant_tables(64, None, None) == adct.E_ARG
