@@ -84,6 +84,13 @@ int adct_abi_version(void);
  * W[u*16+v] = 256 / (d_u d_v), d = diag(T T^T).  Any pointer may be NULL. */
 int adct_constants(int32_t* T256, double* s16, int32_t* W256);
 
+/* Host run of the kernels' fp32 rounding (round half away from zero, the
+ * rule of the quantiser and dequantiser) against (int32_t)roundf for the
+ * fp32 values with bit patterns first_bits .. first_bits + count - 1
+ * (NaNs, infinities and values outside int32 skipped): *mismatches
+ * receives the number that differ.  A check, not a compute call. */
+int adct_round_check(uint32_t first_bits, uint32_t count, int64_t* mismatches);
+
 /* Host copy of the zig-zag ranks the kernels use (Section 3.1's retention
  * order): rank256[u*16+v] = position of coefficient (u, v) in the scan
  * (see adct_zigzag).  ADCT_E_ARG for NULL. */

@@ -94,6 +94,7 @@ _SIGNATURES = {
     "adct_zonal": (ctypes.c_int, [_P, _I64, ctypes.c_int, _P, _P]),
     "adct_zigzag": (ctypes.c_int, [_P, _I64, ctypes.c_int, _P, _P]),
     "adct_zigzag_ranks": (ctypes.c_int, [_P]),
+    "adct_round_check": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32, ctypes.POINTER(_I64)]),
     "adct_zigzag_recon": (ctypes.c_int, [_P, ctypes.c_int, _PP, _PP, _I32, _P, _P]),
     "adct_encode_zigzag": (ctypes.c_int, [_PP, ctypes.c_int, _P, _PP, _I32, _P, _P]),
     "adct_ssim": (ctypes.c_int, [_PP, _PP, _I32, _P, _P]),
@@ -233,6 +234,13 @@ def psnr(sse, pixels_per_image: float, peak: float = 255.0) -> np.ndarray:
     out = np.empty(sse.shape[0], np.float64)
     _check(_lib().adct_psnr(sse.ctypes.data, sse.shape[0], pixels_per_image, peak, out.ctypes.data), "psnr")
     return out
+
+
+def round_check(first_bits: int, count: int) -> int:
+    """Mismatches of the kernels' rounding against roundf over a range of fp32 bit patterns."""
+    n = _I64(0)
+    _check(_lib().adct_round_check(first_bits, count, ctypes.byref(n)), "round_check")
+    return n.value
 
 
 def zigzag_ranks() -> np.ndarray:

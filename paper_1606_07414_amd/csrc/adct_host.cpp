@@ -6,6 +6,7 @@
 
 #include "adct.h"
 #include "adct_internal.hpp"
+#include "adct_round.hpp"
 
 namespace adct {
 
@@ -94,6 +95,21 @@ int adct_constants(int32_t* T256, double* s16, int32_t* W256) {
         if (W256)
             for (int v = 0; v < 16; ++v) W256[u * 16 + v] = 256 / (row_norm(u) * row_norm(v));
     }
+    return ADCT_OK;
+}
+
+int adct_round_check(uint32_t first_bits, uint32_t count, int64_t* mismatches) {
+    if (!mismatches) return ADCT_E_ARG;
+    int64_t bad = 0;
+    for (uint64_t k = 0; k < count; ++k) {
+        const uint32_t bits = first_bits + (uint32_t)k;
+        float x;
+        memcpy(&x, &bits, sizeof x);
+        const float r = roundf(x);
+        if (!(fabsf(r) < 2147483648.0f)) continue;  // NaN, infinity, or outside int32
+        if (round_away(x) != (int32_t)r) ++bad;
+    }
+    *mismatches = bad;
     return ADCT_OK;
 }
 

@@ -221,6 +221,9 @@ __global__ __launch_bounds__(256) void k_t8(Args8 a) {
         }
     }
     if constexpr (OP == kFwd8) return;
+    // the second half starts here: nothing of it (the reloads of the source
+    // rows in particular) is scheduled into the forward half
+    __builtin_amdgcn_sched_barrier(0);
     // retention or dequantisation, into 6 fractional bits
 #pragma unroll
     for (int u = 0; u < 8; ++u)
@@ -250,7 +253,12 @@ __global__ __launch_bounds__(256) void k_t8(Args8 a) {
     for (int i = 0; i < 8; ++i) {
         int32_t row[8], x[8];
         inv8(y[i], row);
-        unpack_row8<S>(raw[i], x);
+        if constexpr (SSE) {
+            // read the source row again (it is still in L2) instead of keeping
+            // the block's input live through the whole computation
+            unpack_row8<S>(load_row8<S>(a.src + (int64_t)(by * 8u + (uint32_t)i) * a.src_pitch +
+                                        (int64_t)bx * 8 * (int64_t)sizeof(S)), x);
+        }
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             // clamp before the shift (floor((R + 32) / 64) lands in [lo, hi])

@@ -2,6 +2,7 @@
 // by the tile kernels.
 #pragma once
 
+#include "adct_round.hpp"
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -97,8 +98,7 @@ __device__ __forceinline__ void column_factors(const Scale5& t, int v, float (&o
     for (int l = 2; l <= 4; ++l) out[l - 2] = pick5(t, l + lv - 4);
 }
 
-// round half away from zero of an fp32 value, as an integer
-__device__ __forceinline__ int32_t round_away(float x) { return (int32_t)roundf(x); }
+
 
 __device__ __forceinline__ int32_t clamp_i32(int32_t x, int32_t lo, int32_t hi) {
     return min(max(x, lo), hi);

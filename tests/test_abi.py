@@ -274,3 +274,16 @@ def test_t8_argument_checks():
     assert lib.adct_t8_fwd2d(ctypes.byref(_plane(FAKE + 8, adct.I16, 8, 8, 16)), FAKE, None) == adct.E_ALIGN
     assert lib.adct_t8_fwd2d(ctypes.byref(_plane(FAKE, adct.I16, 8, 8, 24)), FAKE, None) == adct.E_ALIGN
     assert lib.adct_t8_quant_tables(64, None, None) == adct.E_ARG
+
+
+def test_kernel_rounding_is_round_half_away_for_every_fp32():
+    # every finite fp32 whose rounded value fits an int32, both signs
+    # (bit patterns 0 .. 0x4F000000 are |x| < 2^31)
+    total = 0
+    for sign in (0, 0x80000000):
+        start = sign
+        end = sign + 0x4F000000
+        step = 1 << 28
+        for b in range(start, end, step):
+            total += adct.round_check(b, min(step, end - b))
+    assert total == 0
