@@ -74,7 +74,15 @@ struct Args8 {
     int32_t r;               // zonal size
     float qs[5], dqs[5];     // per class c = log2 d_u + log2 d_v - 2
     unsigned long long* sse; // per image, or null
+    uint32_t spread_rows;    // 0: workgroup b takes chunk b; else see k_t8
 };
+
+// Workgroups of a launch that adds to the SSE of large images are dealt
+// over the plane in this many interleaved streams (as the 16-point group
+// kernel does), so that the workgroups resident at one time add to many
+// images' sums instead of queueing on the atomics of a few.
+constexpr uint32_t kSpread8 = 256;
+constexpr uint32_t kSpreadMin8 = 16;  // chunks of 256 blocks per image
 
 // One block row as raw words (uint8: 8 samples in w.x, w.y; int16: 8
 // samples in w.x .. w.w), and the same unpacked to int32.
@@ -163,8 +171,13 @@ template <typename S, int OP, bool STORE, bool SSE>
 __global__ __launch_bounds__(256) void k_t8(Args8 a) {
     constexpr int kHalf = OP == kQuant8 ? 16 : 32;  // 32-bit words of half a stored block
     __shared__ uint32_t lds[4][64 * (kHalf + 1)];
-    __shared__ long long red[4];
-    const uint32_t g = blockIdx.x * 256u + threadIdx.x;
+    __shared__ long long red[2][4];
+    // chunk of 256 consecutive blocks taken by this workgroup
+    const uint32_t chunk =
+        a.spread_rows ? (blockIdx.x % kSpread8) * a.spread_rows + blockIdx.x / kSpread8 : blockIdx.x;
+    const uint32_t first = chunk * 256u;
+    if (first >= a.nblk) return;  // past the last chunk (spread grids only)
+    const uint32_t g = first + threadIdx.x;
     const bool ok = g < a.nblk;
     const uint32_t gs = ok ? g : a.nblk - 1;
     const uint32_t by = fdiv(gs, a.bwdiv), bx = gs - by * a.bw;
@@ -190,7 +203,7 @@ __global__ __launch_bounds__(256) void k_t8(Args8 a) {
         for (int u = 0; u < 8; ++u) y[u][v] = o[u];
     }
     const int wave = threadIdx.x >> 6;
-    const uint32_t wave_first = blockIdx.x * 256u + (uint32_t)wave * 64u;
+    const uint32_t wave_first = first + (uint32_t)wave * 64u;
     const uint32_t nvalid = a.nblk > wave_first ? min(64u, a.nblk - wave_first) : 0u;
     if constexpr (OP == kQuant8) {
 #pragma unroll
@@ -272,18 +285,28 @@ __global__ __launch_bounds__(256) void k_t8(Args8 a) {
     }
     if constexpr (SSE) {
         if (!ok) sse = 0;
-        // blocks of one workgroup may belong to different images
-        const uint32_t first = blockIdx.x * 256u, last = min(a.nblk, first + 256u) - 1u;
+        // the blocks of one workgroup lie in at most two images unless the
+        // images are smaller than a workgroup's 256 blocks
+        const uint32_t last = min(a.nblk, first + 256u) - 1u;
         const uint32_t img0 = fdiv(fdiv(first, a.bwdiv), a.ipbdiv), img1 = fdiv(fdiv(last, a.bwdiv), a.ipbdiv);
-        if (img0 == img1) {
-            long long v = sse;
+        if (img1 - img0 <= 1u) {
+            const bool in0 = !ok || fdiv(by, a.ipbdiv) == img0;
+            long long v0 = in0 ? sse : 0, v1 = in0 ? 0 : sse;
 #pragma unroll
-            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-            if ((threadIdx.x & 63) == 0) red[wave] = v;
+            for (int off = 32; off > 0; off >>= 1) {
+                v0 += __shfl_xor(v0, off, 64);
+                v1 += __shfl_xor(v1, off, 64);
+            }
+            if ((threadIdx.x & 63) == 0) {
+                red[0][wave] = v0;
+                red[1][wave] = v1;
+            }
             __syncthreads();
             if (threadIdx.x == 0) {
-                const long long t = red[0] + red[1] + red[2] + red[3];
-                if (t) atomicAdd(a.sse + img0, (unsigned long long)t);
+                const long long t0 = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+                const long long t1 = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+                if (t0) atomicAdd(a.sse + img0, (unsigned long long)t0);
+                if (t1) atomicAdd(a.sse + img1, (unsigned long long)t1);
             }
         } else if (ok && sse) {
             atomicAdd(a.sse + fdiv(by, a.ipbdiv), (unsigned long long)sse);
@@ -363,7 +386,7 @@ bool quant_scales8(int qp, float* qs, float* dqs) {
 
 template <typename S, int OP, bool STORE>
 void launch8(const Args8& a, hipStream_t s) {
-    const dim3 grid((a.nblk + 255) / 256);
+    const dim3 grid(a.spread_rows ? a.spread_rows * kSpread8 : (a.nblk + 255) / 256);
     if (a.sse)
         hipLaunchKernelGGL((k_t8<S, OP, STORE, true>), grid, dim3(256), 0, s, a);
     else
@@ -402,6 +425,9 @@ int setup_encoder(const adct_plane* src, void* coef, const adct_plane* dst, int3
     a.ipbdiv = make_fastdiv(sse ? (uint32_t)(image_height / 8) : 1u);
     a.sse = reinterpret_cast<unsigned long long*>(sse);
     if (sse) {
+        const uint32_t chunks = (a.nblk + 255) / 256;
+        const uint32_t image_blocks = (uint32_t)(image_height / 8) * a.bw;
+        if (image_blocks / 256 > kSpreadMin8) a.spread_rows = (chunks + kSpread8 - 1) / kSpread8;
         const uint32_t nimg = (uint32_t)(src->height / image_height);
         hipLaunchKernelGGL(k_t8_zero, dim3((nimg + 255) / 256), dim3(256), 0, s, a.sse, nimg);
         return launched();

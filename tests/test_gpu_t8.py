@@ -108,3 +108,25 @@ def test_t8_video_frames_full_size():
             _, want = E8.quant_reconstruct8(plane, qp)
             assert np.array_equal(host(out), want), qp
             assert s[0] == O.sse(want, plane)
+
+
+@pytest.mark.parametrize("op", ["zonal", "quant"])
+def test_t8_sse_over_large_images_spread_and_split(op):
+    # 544 x 960 images: 8160 blocks each, so workgroups of 256 blocks cross
+    # image boundaries and the launch interleaves its workgroups
+    n, h, w = 5, 544, 960
+    if op == "zonal":
+        src = synth.ar1_batch(n, h, w, seed_base=2400)
+    else:
+        src = np.concatenate([synth.laplacian_residual(2400 + i, h, w) for i in range(n)])
+    x = dev(src)
+    out = torch.empty_like(x)
+    if op == "zonal":
+        s = host(adct.t8_encode_zonal(x, 3, out, image_height=h))
+        want = E8.zonal_reconstruct8(src, 3)
+    else:
+        s = host(adct.t8_encode_quant(x, 32, out, image_height=h))
+        _, want = E8.quant_reconstruct8(src, 32)
+    assert np.array_equal(host(out), want)
+    for i in range(n):
+        assert s[i] == O.sse(want[i * h:(i + 1) * h], src[i * h:(i + 1) * h]), i
