@@ -172,3 +172,24 @@ def test_t8_wrong_rounding_offset_is_caught(monkeypatch):
     monkeypatch.setattr(E8, "round_clamp8",
                         lambda R, lo, hi: np.clip(np.floor_divide(np.asarray(R, np.int64), 64), lo, hi))
     assert _fails(P8.test_zonal8_special_cases)
+
+
+# ---- comparison transforms ----
+from oracle import comparison as CMP  # noqa: E402
+import tests.test_oracle_comparison as PC  # noqa: E402
+
+
+def test_wht_sequency_order_is_caught(monkeypatch):
+    H = CMP.wht_matrix()
+    seq = np.argsort([np.count_nonzero(np.diff(row)) for row in H])  # rows by sign changes
+    monkeypatch.setattr(CMP, "wht_matrix", lambda: H[seq].copy())
+    assert _fails(PC.test_wht_is_the_natural_order_hadamard)
+    assert _fails(PC.test_wht_fast_algorithm_has_64_additions)
+
+
+def test_dct_rounding_down_is_caught(monkeypatch):
+    real = CMP.dct_reconstruct_real
+    monkeypatch.setattr(CMP, "dct_reconstruct",
+                        lambda img, kind, r, lo=0, hi=255: np.clip(np.floor(real(img, kind, r)), lo, hi)
+                        .astype(np.uint8))
+    assert _fails(PC.test_dct_reconstruction_special_cases)
