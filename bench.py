@@ -133,6 +133,10 @@ def single_image(torch, adct, stream):
 
 ZIGZAG_R = (1, 3, 6, 10, 15, 21, 28, 36, 45, 55, 66, 78, 91, 105, 120, 136, 150)
 ADDITIONS = 44  # additions of one 16-point transform (Table 1)
+# arithmetic operations of one 16-point transform (Table 1 totals): the
+# proposed approximation, the WHT and the Chen DCT (44 mult + 74 add)
+OPS = {"proposed": 44, "wht": 64, "dct": 118}
+COMPARE_R = ((0, 2), (0, 4), (0, 8), (1, 3), (1, 10), (1, 21), (1, 45), (1, 105), (1, 150))
 
 
 def image_experiment(torch, adct, stream, x, coef, out, n_img):
@@ -155,6 +159,20 @@ def image_experiment(torch, adct, stream, x, coef, out, n_img):
                        "encoder_ms": ms_enc, "encoder_tiles_per_s": ntiles / (ms_enc * 1e-3), "encoder_gbs": gbs,
                        "encoder_frac_of_8tbs": gbs / HBM_PEAK_GBS, "ssim_ms": ms_ssim,
                        "ssim_images_per_s": n_img / (ms_ssim * 1e-3)}
+    # Tables 1 and 2's comparison transforms through the same codec
+    cmp = {}
+    for kind, r in COMPARE_R:
+        row = {}
+        for name, xf in (("proposed", adct.XF_PROPOSED), ("wht", adct.XF_WHT), ("dct", adct.XF_DCT)):
+            ms = timed(torch, lambda: adct.compare_encode(x, xf, kind, r, out, image_height=SIDE, sse=sse,
+                                                          stream=stream), 3, stream)
+            adct.ssim(x, out, image_height=SIDE, out=ss, stream=stream)
+            p = float(np.mean(adct.psnr(sse.cpu().numpy(), SIDE * SIDE)))
+            m = float(ss.mean().item())
+            row[name] = {"psnr_db": p, "ssim": m, "psnr_per_op": p / OPS[name], "ssim_per_op": m / OPS[name],
+                         "ms": ms, "tiles_per_s": ntiles / (ms * 1e-3)}
+        cmp[("zonal_r%d" if kind == 0 else "zigzag_r%d") % r] = row
+    res["comparison"] = {"ops_per_16_point_transform": OPS, "retention": cmp}
     return res
 
 

@@ -110,10 +110,11 @@ int adct_psnr(const int64_t* sse, int32_t n, double pixels_per_image, double pea
               double* out);
 
 /* The kernels' own 1D butterflies executed on the host (the same source the
- * GPU runs): X = T x (inverse = 0) or x = T^T X (inverse = 1), Section 2.2's
- * 44-addition dataflow.  For checking the dataflow without a GPU.
- * in16, out16: host int32[16]. */
-int adct_host_butterfly(int32_t inverse, const int32_t* in16, int32_t* out16);
+ * GPU runs): X = T x (which = 0) or x = T^T X (which = 1), Section 2.2's
+ * 44-addition dataflow, or the comparison WHT X = H x (which = 2, natural
+ * order, 64 additions).  For checking the dataflows without a GPU.
+ * in16, out16: host int32[16]; ADCT_E_ARG for another `which`. */
+int adct_host_butterfly(int32_t which, const int32_t* in16, int32_t* out16);
 
 /* ---- plain device calls -------------------------------------------------- */
 
@@ -228,6 +229,33 @@ int adct_encode_zigzag(const adct_plane* src, int r, int32_t* coef, const adct_p
  * adct_fwd2d_quant + adct_dequant_recon. */
 int adct_encode_quant(const adct_plane* src, int qp, int16_t* q, const adct_plane* dst,
                       int32_t image_height, int64_t* sse, void* stream);
+
+/* ---- comparison transforms through the same codec ----------------------- */
+/* Tables 1 and 2 compare the approximation with the exact DCT and with the
+ * Walsh-Hadamard transform; this call runs any of the three through Section
+ * 3.1's codec on 16x16 blocks: forward, retention, inverse, rounding half up
+ * and clamping into dst, and the optional exact per-image SSE.
+ *   ADCT_XF_PROPOSED  T, as adct_encode_zonal / adct_encode_zigzag (bit-exact).
+ *   ADCT_XF_WHT       natural-order Hadamard H (H[k][j] = (-1)^popcount(k&j)),
+ *                     integer and exact: H H^T = 16 I, so the normalisation
+ *                     weights are all 1 and R = H^T Z H carries 8 fractional
+ *                     bits; 64 additions per 16-point pass.
+ *   ADCT_XF_DCT       the orthonormal DCT-II C in fp32 on the matrix cores:
+ *                     B = C A C^T, retention, X = C^T B C, output
+ *                     clamp(floor(X + 1/2)).  Differs from a float64
+ *                     evaluation only where X lies within about 1e-3 of a
+ *                     rounding boundary.
+ * retention: ADCT_KEEP_ZONAL (top-left r x r, r in [0, 16]) or
+ * ADCT_KEEP_ZIGZAG (first r of the zig-zag scan, r in [0, 256]).  Planes as
+ * for adct_encode_zonal (U8 or I16); no coefficients are written. */
+#define ADCT_XF_PROPOSED 0
+#define ADCT_XF_WHT      1
+#define ADCT_XF_DCT      2
+#define ADCT_KEEP_ZONAL  0
+#define ADCT_KEEP_ZIGZAG 1
+
+int adct_compare_encode(const adct_plane* src, int32_t transform, int32_t retention, int r, const adct_plane* dst,
+                        int32_t image_height, int64_t* sse, void* stream);
 
 /* ---- the 8-point transform T8 on 8x8 blocks ---------------------------- */
 /* T is built from two instances of the 8-point approximation T8 (Section

@@ -46,6 +46,8 @@ class Tune(ctypes.Structure):
 
 
 OP_ZONAL, OP_QUANT, OP_ZIGZAG = 1, 2, 3
+XF_PROPOSED, XF_WHT, XF_DCT = 0, 1, 2
+KEEP_ZONAL, KEEP_ZIGZAG = 0, 1
 SERVE_PERSISTENT, SERVE_PLAIN = 0, 1
 
 
@@ -98,6 +100,7 @@ _SIGNATURES = {
     "adct_zigzag_recon": (ctypes.c_int, [_P, ctypes.c_int, _PP, _PP, _I32, _P, _P]),
     "adct_encode_zigzag": (ctypes.c_int, [_PP, ctypes.c_int, _P, _PP, _I32, _P, _P]),
     "adct_ssim": (ctypes.c_int, [_PP, _PP, _I32, _P, _P]),
+    "adct_compare_encode": (ctypes.c_int, [_PP, _I32, _I32, ctypes.c_int, _PP, _I32, _P, _P]),
     "adct_t8_constants": (ctypes.c_int, [_P, _P, _P]),
     "adct_t8_quant_tables": (ctypes.c_int, [ctypes.c_int, _P, _P]),
     "adct_t8_fwd2d": (ctypes.c_int, [_PP, _P, _P]),
@@ -250,10 +253,11 @@ def zigzag_ranks() -> np.ndarray:
     return r.reshape(16, 16)
 
 
-def host_butterfly(x, inverse: bool = False) -> np.ndarray:
+def host_butterfly(x, inverse: bool = False, wht: bool = False) -> np.ndarray:
     x = np.ascontiguousarray(np.asarray(x, dtype=np.int32).reshape(16))
     y = np.empty(16, np.int32)
-    _check(_lib().adct_host_butterfly(1 if inverse else 0, x.ctypes.data, y.ctypes.data), "host_butterfly")
+    which = 2 if wht else (1 if inverse else 0)
+    _check(_lib().adct_host_butterfly(which, x.ctypes.data, y.ctypes.data), "host_butterfly")
     return y
 
 
@@ -452,6 +456,16 @@ def t8_encode_quant(src, qp: int, dst, q=None, image_height=None, sse=None, want
     ih, sse, sp = _sse_out(src, image_height, sse, want_sse)
     _check(_lib().adct_t8_encode_quant(ctypes.byref(ps), qp, q.data_ptr() if q is not None else None,
                                        ctypes.byref(pd), ih, sp, _stream(stream)), "t8_encode_quant")
+    return sse
+
+
+def compare_encode(src, transform: int, retention: int, r: int, dst, image_height=None, sse=None, want_sse=True,
+                   stream=None):
+    """Codec with a comparison transform (XF_PROPOSED / XF_WHT / XF_DCT); returns the per-image SSE."""
+    ps, pd = plane(src), plane(dst)
+    ih, sse, sp = _sse_out(src, image_height, sse, want_sse)
+    _check(_lib().adct_compare_encode(ctypes.byref(ps), transform, retention, r, ctypes.byref(pd), ih, sp,
+                                      _stream(stream)), "compare_encode")
     return sse
 
 

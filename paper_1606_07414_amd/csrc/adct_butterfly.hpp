@@ -117,4 +117,63 @@ __host__ __device__ __forceinline__ void inv16(const V (&X)[16], V (&x)[16]) {
     x[8] = p7 - p8;
 }
 
+// The natural-order Walsh-Hadamard transform of order 16 (H[k][j] =
+// (-1)^popcount(k & j)), the WHT row of Table 2, used as a comparison
+// transform: butterflies (a + b, a - b) at strides 8, 4, 2, 1, 64 additions.
+// H^T = H, so the same dataflow is its inverse (up to the factor 16).
+template <typename V>
+__host__ __device__ __forceinline__ void wht16(const V (&x)[16], V (&X)[16]) {
+    V a[16], b[16];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        a[i] = x[i] + x[i + 8];
+        a[i + 8] = x[i] - x[i + 8];
+    }
+#pragma unroll
+    for (int i = 0; i < 16; i += 8)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            b[i + j] = a[i + j] + a[i + j + 4];
+            b[i + j + 4] = a[i + j] - a[i + j + 4];
+        }
+#pragma unroll
+    for (int i = 0; i < 16; i += 4)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            a[i + j] = b[i + j] + b[i + j + 2];
+            a[i + j + 2] = b[i + j] - b[i + j + 2];
+        }
+#pragma unroll
+    for (int i = 0; i < 16; i += 2) {
+        X[i] = a[i] + a[i + 1];
+        X[i + 1] = a[i] - a[i + 1];
+    }
+}
+
+// Transform selection of the group kernel: the proposed T (default) or the
+// WHT.  lnorm is log2 of the squared row norm d_k (T: from the table above;
+// WHT: 16 for every row).
+enum Xform { kXfProposed = 0, kXfWht = 1 };
+
+template <int XF, typename V>
+__host__ __device__ __forceinline__ void xf_fwd(const V (&x)[16], V (&X)[16]) {
+    if constexpr (XF == kXfWht)
+        wht16(x, X);
+    else
+        fwd16(x, X);
+}
+
+template <int XF, typename V>
+__host__ __device__ __forceinline__ void xf_inv(const V (&X)[16], V (&x)[16]) {
+    if constexpr (XF == kXfWht)
+        wht16(X, x);
+    else
+        inv16(X, x);
+}
+
+template <int XF>
+__host__ __device__ constexpr int xf_lnorm(int k) {
+    return XF == kXfWht ? 4 : log2_norm(k);
+}
+
 }  // namespace adct

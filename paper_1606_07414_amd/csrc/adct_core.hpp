@@ -64,9 +64,10 @@ enum CStore { kStoreNone = 0, kStoreY = 1, kStoreQ = 2 };
 enum Mid { kMidNone = 0, kMidZonal = 1, kMidQuant = 2, kMidDequant = 3, kMidZigzag = 4 };
 enum OutKind { kOutNothing = 0, kOutSamples = 1, kOutBlocks = 2 };
 
-template <int IN_, int STORE_, int MID_, int OUT_, int ZR_, bool SSE_>
+// XF selects the transform: kXfProposed (T) or kXfWht (comparison).
+template <int IN_, int STORE_, int MID_, int OUT_, int ZR_, bool SSE_, int XF_ = kXfProposed>
 struct Mode {
-    static constexpr int IN = IN_, STORE = STORE_, MID = MID_, OUT = OUT_, ZR = ZR_;
+    static constexpr int IN = IN_, STORE = STORE_, MID = MID_, OUT = OUT_, ZR = ZR_, XF = XF_;
     static constexpr bool SSE = SSE_;
 };
 
@@ -155,14 +156,14 @@ struct RowWords {
     uint4 a0, a1, b0, b1;
 };
 
-template <typename S>
+template <typename S, int XF>
 __device__ __forceinline__ void fwd_rows(const RowWords& w, int lt, int ip, uint32_t* lds, uint32_t (&xk)[16]) {
     pack_rows<S>(w.a0, w.a1, w.b0, w.b1, xk);
     u16x2 x[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) x[k] = as_u16x2(xk[k]);
     u16x2 z[16];
-    fwd16(x, z);
+    xf_fwd<XF>(x, z);
     uint32_t w0[8], w1[8];
 #pragma unroll
     for (int p = 0; p < 8; ++p) {
@@ -179,7 +180,7 @@ __device__ __forceinline__ void fwd_rows(const RowWords& w, int lt, int ip, uint
 
 // ---- forward column pass (column role) ------------------------------------
 // ya[u] = Y[u][p], yb[u] = Y[u][p+8] as int32.
-template <typename S>
+template <typename S, int XF>
 __device__ __forceinline__ void fwd_columns(const uint32_t* lds, int lt, int p, int32_t (&ya)[16],
                                             int32_t (&yb)[16]) {
     uint32_t w[16];
@@ -190,7 +191,7 @@ __device__ __forceinline__ void fwd_columns(const uint32_t* lds, int lt, int p, 
         u16x2 z[16], y[16];
 #pragma unroll
         for (int k = 0; k < 16; ++k) z[k] = as_u16x2(w[k]);
-        fwd16(z, y);
+        xf_fwd<XF>(z, y);
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
             const uint32_t t = as_u32(y[u]);
@@ -206,8 +207,8 @@ __device__ __forceinline__ void fwd_columns(const uint32_t* lds, int lt, int p, 
             za[k] = sext_lo(w[k]);
             zb[k] = sext_hi(w[k]);
         }
-        fwd16(za, ya);
-        fwd16(zb, yb);
+        xf_fwd<XF>(za, ya);
+        xf_fwd<XF>(zb, yb);
     }
 }
 
@@ -324,26 +325,27 @@ __device__ __forceinline__ void lds_get_q_columns(const uint32_t* lds, int lt, i
 // ---- coefficient domain ----------------------------------------------------
 // Zonal retention with the S weights; r fixed at compile time (ZR >= 0) or
 // at run time.
-template <int ZR>
+template <int ZR, int XF>
 __device__ __forceinline__ void zonal_weights_cols(int p, int rr, int32_t (&a)[16], int32_t (&b)[16]) {
     const int r = ZR >= 0 ? ZR : rr;
-    const int la = log2_norm(p), lb = log2_norm(p + 8);
+    const int la = xf_lnorm<XF>(p), lb = xf_lnorm<XF>(p + 8);
     const bool ka = p < r, kb = p + 8 < r;
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
         const bool ku = ZR >= 0 ? (u < ZR) : (u < r);
-        const int su = 8 - log2_norm(u);
+        const int su = 8 - xf_lnorm<XF>(u);
         a[u] = (ku && ka) ? (int32_t)((uint32_t)a[u] << (su - la)) : 0;
         b[u] = (ku && kb) ? (int32_t)((uint32_t)b[u] << (su - lb)) : 0;
     }
 }
 
 // Zig-zag retention of the first r coefficients with the S weights.
+template <int XF>
 __device__ __forceinline__ void zigzag_weights_cols(int p, int r, int32_t (&a)[16], int32_t (&b)[16]) {
-    const int la = log2_norm(p), lb = log2_norm(p + 8);
+    const int la = xf_lnorm<XF>(p), lb = xf_lnorm<XF>(p + 8);
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
-        const int su = 8 - log2_norm(u);
+        const int su = 8 - xf_lnorm<XF>(u);
         a[u] = zigzag_rank(u, p) < r ? (int32_t)((uint32_t)a[u] << (su - la)) : 0;
         b[u] = zigzag_rank(u, p + 8) < r ? (int32_t)((uint32_t)b[u] << (su - lb)) : 0;
     }
@@ -455,10 +457,10 @@ __device__ __forceinline__ void process_group(const GroupArgs& a, uint32_t g0, u
 
     // ---------------- input --------------------------------------------------
     if constexpr (M::IN == kInSamples) {
-        fwd_rows<S>(rows, rlt, rip, lds, xk);
+        fwd_rows<S, M::XF>(rows, rlt, rip, lds, xk);
         if (ntn) load_group_rows<TPW, S>(an, g0n, ntn, rows);
         __syncthreads();
-        fwd_columns<S>(lds, clt, cp, ya, yb);
+        fwd_columns<S, M::XF>(lds, clt, cp, ya, yb);
     } else {
         if constexpr (M::SSE) {
             // prefetch the reference rows so their latency overlaps the rest
@@ -517,9 +519,9 @@ __device__ __forceinline__ void process_group(const GroupArgs& a, uint32_t g0, u
     } else if constexpr (M::MID == kMidDequant) {
         dequant_cols(dqs, cp, ya, yb);
     } else if constexpr (M::MID == kMidZonal) {
-        zonal_weights_cols<M::ZR>(cp, a.r, ya, yb);
+        zonal_weights_cols<M::ZR, M::XF>(cp, a.r, ya, yb);
     } else if constexpr (M::MID == kMidZigzag) {
-        zigzag_weights_cols(cp, a.r, ya, yb);
+        zigzag_weights_cols<M::XF>(cp, a.r, ya, yb);
     }
 
     if constexpr (M::OUT == kOutNothing) return;
@@ -530,8 +532,8 @@ __device__ __forceinline__ void process_group(const GroupArgs& a, uint32_t g0, u
     }
     {
         int32_t qa[16], qb[16];
-        inv16(ya, qa);
-        inv16(yb, qb);
+        xf_inv<M::XF>(ya, qa);
+        xf_inv<M::XF>(yb, qb);
         __syncthreads();
         lds_put_columns(lds, clt, cp, qa, qb);
         __syncthreads();
@@ -540,9 +542,9 @@ __device__ __forceinline__ void process_group(const GroupArgs& a, uint32_t g0, u
     {
         int32_t q[16];
         lds_get_row(lds, rlt, rip, q);
-        inv16(q, r0);
+        xf_inv<M::XF>(q, r0);
         lds_get_row(lds, rlt, rip + 8, q);
-        inv16(q, r1);
+        xf_inv<M::XF>(q, r1);
     }
     if constexpr (M::OUT == kOutBlocks) {
         if (rok) {

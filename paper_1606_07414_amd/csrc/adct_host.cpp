@@ -177,11 +177,13 @@ int adct_work_queue(const int64_t* tiles_per_job, int32_t njobs, int32_t tiles_p
 
 // Host execution of the kernels' 1D butterflies (the same code the GPU
 // runs), for checking the dataflow without a GPU.
-int adct_host_butterfly(int32_t inverse, const int32_t* in16, int32_t* out16) {
-    if (!in16 || !out16) return ADCT_E_ARG;
+int adct_host_butterfly(int32_t which, const int32_t* in16, int32_t* out16) {
+    if (!in16 || !out16 || which < 0 || which > 2) return ADCT_E_ARG;
     int32_t x[16], y[16];
     memcpy(x, in16, sizeof x);
-    if (inverse)
+    if (which == 2)
+        wht16(x, y);
+    else if (which == 1)
         inv16(x, y);
     else
         fwd16(x, y);

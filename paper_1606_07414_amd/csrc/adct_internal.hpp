@@ -20,6 +20,10 @@ void ortho_scales(Scale5Host* ss);
 // class c = log2 d_u + log2 d_v - 4 of coefficient (u, v).
 int class_of(int u, int v);
 
+// Exact-DCT comparison codec (adct_compare.hip); arguments already checked.
+int launch_dct_codec(const adct_plane* src, int32_t kind, int r, const adct_plane* dst, int32_t image_height,
+                     int64_t* sse, void* stream);
+
 inline int sample_bytes(int32_t dtype) { return dtype == ADCT_U8 ? 1 : dtype == ADCT_I16 ? 2 : 0; }
 
 // Validate a plane descriptor (see the conventions in adct.h).

@@ -341,6 +341,38 @@ int adct_encode_zigzag(const adct_plane* src, int r, int32_t* coef, const adct_p
                : launch_typed<Mode<kInSamples, kStoreNone, kMidZigzag, kOutSamples, -1, false>>(dt, n, s, a);
 }
 
+int adct_compare_encode(const adct_plane* src, int32_t transform, int32_t retention, int r, const adct_plane* dst,
+                        int32_t image_height, int64_t* sse, void* stream) {
+    if (retention != ADCT_KEEP_ZONAL && retention != ADCT_KEEP_ZIGZAG) return ADCT_E_ARG;
+    if (r < 0 || r > (retention == ADCT_KEEP_ZONAL ? 16 : 256)) return ADCT_E_ARG;
+    if (transform != ADCT_XF_PROPOSED && transform != ADCT_XF_WHT && transform != ADCT_XF_DCT) return ADCT_E_ARG;
+    int rc = check_plane(src);
+    if (rc) return rc;
+    if ((rc = check_plane(dst))) return rc;
+    if (!same_shape(src, dst)) return ADCT_E_SHAPE;
+    if (sse && (image_height <= 0 || (image_height & 15) || src->height % image_height)) return ADCT_E_SHAPE;
+    if (sse && ((uintptr_t)sse & 7)) return ADCT_E_ALIGN;
+    if (transform == ADCT_XF_PROPOSED)
+        return retention == ADCT_KEEP_ZONAL ? adct_encode_zonal(src, r, nullptr, dst, image_height, sse, stream)
+                                            : adct_encode_zigzag(src, r, nullptr, dst, image_height, sse, stream);
+    if (transform == ADCT_XF_DCT) return launch_dct_codec(src, retention, r, dst, image_height, sse, stream);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    GroupArgs a{};
+    a.src = plane_ref(src);
+    set_geometry(src, a);
+    a.dst = plane_ref(dst);
+    set_geometry(dst, a);
+    a.r = r;
+    if ((rc = prepare_sse(dst, src, image_height, sse, s, a))) return rc;
+    const uint32_t n = (uint32_t)plane_blocks(src);
+    const int32_t dt = src->dtype;
+    if (retention == ADCT_KEEP_ZONAL)
+        return sse ? launch_typed<Mode<kInSamples, kStoreNone, kMidZonal, kOutSamples, -1, true, kXfWht>>(dt, n, s, a)
+                   : launch_typed<Mode<kInSamples, kStoreNone, kMidZonal, kOutSamples, -1, false, kXfWht>>(dt, n, s, a);
+    return sse ? launch_typed<Mode<kInSamples, kStoreNone, kMidZigzag, kOutSamples, -1, true, kXfWht>>(dt, n, s, a)
+               : launch_typed<Mode<kInSamples, kStoreNone, kMidZigzag, kOutSamples, -1, false, kXfWht>>(dt, n, s, a);
+}
+
 int adct_encode_quant(const adct_plane* src, int qp, int16_t* q, const adct_plane* dst, int32_t image_height,
                       int64_t* sse, void* stream) {
     Scale5Host qs, dqs;

@@ -287,3 +287,28 @@ def test_kernel_rounding_is_round_half_away_for_every_fp32():
         for b in range(start, end, step):
             total += adct.round_check(b, min(step, end - b))
     assert total == 0
+
+
+def test_compare_argument_checks():
+    lib = adct.lib()
+    p = _plane(FAKE, adct.U8, 32, 32, 32)
+    assert lib.adct_compare_encode(ctypes.byref(p), 3, 0, 4, ctypes.byref(p), 32, None, None) == adct.E_ARG
+    assert lib.adct_compare_encode(ctypes.byref(p), 1, 2, 4, ctypes.byref(p), 32, None, None) == adct.E_ARG
+    assert lib.adct_compare_encode(ctypes.byref(p), 2, 0, 17, ctypes.byref(p), 32, None, None) == adct.E_ARG
+    assert lib.adct_compare_encode(ctypes.byref(p), 2, 1, 257, ctypes.byref(p), 32, None, None) == adct.E_ARG
+    q = _plane(FAKE, adct.U8, 16, 32, 32)
+    assert lib.adct_compare_encode(ctypes.byref(p), 1, 0, 4, ctypes.byref(q), 32, None, None) == adct.E_SHAPE
+
+
+def test_kernel_wht_butterfly_on_host():
+    from oracle import comparison as CMP
+    H = CMP.wht_matrix()
+    for k in range(16):
+        e = np.zeros(16, np.int32)
+        e[k] = 1
+        assert np.array_equal(adct.host_butterfly(e, wht=True), H[:, k])
+    rng = np.random.default_rng(16)
+    for x in rng.integers(-(1 << 20), 1 << 20, size=(5000, 16)):
+        assert np.array_equal(adct.host_butterfly(x, wht=True), H @ x)
+    assert adct.lib().adct_host_butterfly(3, np.zeros(16, np.int32).ctypes.data,
+                                          np.zeros(16, np.int32).ctypes.data) == adct.E_ARG
