@@ -22,6 +22,9 @@ beside it.
                  SSIM index (Section 3.1 as the paper runs it).
 ``t8``           the 8-point approximation T8 that T is built from, and its
                  8x8 blockwise codec (Section 3.2's second scenario).
+``mixed``        mixed 8/16-point coding: per 16x16 region, one 16x16 block
+                 or four 8x8 blocks by the lower Lagrangian cost (Section
+                 3.2's second scenario).
 ``comparison``   the WHT and exact-DCT codecs (Tables 1 and 2's comparison
                  transforms through Section 3.1's experiment).
 ``c/``           the same plain dense definition of the 2D forward and

@@ -193,3 +193,44 @@ def test_dct_rounding_down_is_caught(monkeypatch):
                         lambda img, kind, r, lo=0, hi=255: np.clip(np.floor(real(img, kind, r)), lo, hi)
                         .astype(np.uint8))
     assert _fails(PC.test_dct_reconstruction_special_cases)
+
+
+def test_mixed_decision_reversed_is_caught(monkeypatch):
+    from oracle import mixed as X
+    import tests.test_oracle_mixed as PM
+    monkeypatch.setattr(X, "keep_8x8", lambda j16, j8: j8 > j16)
+    assert _fails(PM.test_choice_minimises_the_lagrangian_cost, 27, 5)
+
+
+def test_mixed_tie_to_8x8_is_caught(monkeypatch):
+    from oracle import mixed as X
+    import tests.test_oracle_mixed as PM
+    monkeypatch.setattr(X, "keep_8x8", lambda j16, j8: j8 <= j16)
+    assert _fails(PM.test_constant_quadrants_choose_8x8)
+
+
+def test_mixed_sub_blocks_transposed_is_caught(monkeypatch):
+    from oracle import mixed as X
+    import tests.test_oracle_mixed as PM
+    good = X._region_of_8x8_levels
+
+    def bad(q8, H, W):
+        r = good(q8, H, W).copy()
+        r[:, :8, 8:], r[:, 8:, :8] = r[:, 8:, :8].copy(), r[:, :8, 8:].copy()
+        return r
+    monkeypatch.setattr(X, "_region_of_8x8_levels", bad)
+    assert _fails(PM.test_decoding_the_levels_reproduces_the_output, 32, 30, "i16")
+    assert _fails(PM.test_sub_block_placement)
+
+
+def test_mixed_rate_of_one_sub_block_is_caught(monkeypatch):
+    from oracle import mixed as X
+    import tests.test_oracle_mixed as PM
+    good = X.region_costs
+
+    def bad(plane, qp, lo, hi):
+        c = good(plane, qp, lo, hi)
+        c["R8"] = (c["q8"][:, :8, :8] != 0).sum(axis=(1, 2))
+        return c
+    monkeypatch.setattr(X, "region_costs", bad)
+    assert _fails(PM.test_choice_minimises_the_lagrangian_cost, 37, 200)
