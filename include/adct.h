@@ -111,8 +111,10 @@ int adct_psnr(const int64_t* sse, int32_t n, double pixels_per_image, double pea
 
 /* The kernels' own 1D butterflies executed on the host (the same source the
  * GPU runs): X = T x (which = 0) or x = T^T X (which = 1), Section 2.2's
- * 44-addition dataflow, or the comparison WHT X = H x (which = 2, natural
- * order, 64 additions).  For checking the dataflows without a GPU.
+ * 44-addition dataflow, the comparison WHT X = H x (which = 2, natural
+ * order, 64 additions), or the 8-point T8 (which = 3) or T8^T (which = 4)
+ * applied to each half of the 16 values (14 additions each), as the 8x8 and
+ * mixed codecs apply it.  For checking the dataflows without a GPU.
  * in16, out16: host int32[16]; ADCT_E_ARG for another `which`. */
 int adct_host_butterfly(int32_t which, const int32_t* in16, int32_t* out16);
 
@@ -298,6 +300,34 @@ int adct_t8_encode_zonal(const adct_plane* src, int r, int32_t* coef, const adct
  * optional SSE. */
 int adct_t8_encode_quant(const adct_plane* src, int qp, int16_t* q, const adct_plane* dst,
                          int32_t image_height, int64_t* sse, void* stream);
+
+/* ---- mixed 8/16-point coding ------------------------------------------ */
+/* The codec of the second video scenario of Section 3.2, in which both the
+ * 8-point (T8) and the 16-point (T) transforms are the approximations.  The
+ * paper does not describe how the encoder picks a block's transform size;
+ * here every 16x16 region is coded twice at the same QP, as one 16x16 block
+ * (exactly as adct_encode_quant codes it) and as four 8x8 blocks (exactly
+ * as adct_t8_encode_quant codes them), and keeps the coding with the lower
+ * cost J = D + lambda * R, D the region's exact sum of squared
+ * reconstruction errors and R its number of nonzero levels; equal costs
+ * keep the 16x16 coding.  The decision is integer and exact.
+ *
+ * src, dst: planes as for adct_encode_quant (U8 or I16, sides multiples of
+ * 16, same shape and type), dst receives the chosen reconstruction (clamped
+ * to [0, 255] for U8, [-255, 255] for I16).
+ * qp: [0, 63].  lambda: [0, ADCT_MIXED_MAX_LAMBDA] (else ADCT_E_ARG).
+ * q: device int16 [nreg][16][16], 16-byte aligned, or NULL: the chosen levels
+ *    of region k = by * (width/16) + bx, element u*16 + v; for a split
+ *    region, 8x8 block (a, b) (a vertical) puts its element (i, j) at
+ *    u = 8a + i, v = 8b + j.
+ * split: device uint8 [nreg] or NULL: 1 where the region is coded as four
+ *    8x8 blocks, else 0.
+ * sse: device int64 [height / image_height] or NULL: per-image SSE of dst
+ *    against src (image_height a multiple of 16 dividing the height).
+ * Asynchronous on `stream`; allocates nothing. */
+#define ADCT_MIXED_MAX_LAMBDA (((int64_t)1) << 40)
+int adct_mixed_encode(const adct_plane* src, int qp, int64_t lambda, int16_t* q, uint8_t* split,
+                      const adct_plane* dst, int32_t image_height, int64_t* sse, void* stream);
 
 /* ---- image quality ----------------------------------------------------- */
 

@@ -107,6 +107,7 @@ _SIGNATURES = {
     "adct_t8_inv2d": (ctypes.c_int, [_P, _I64, _P, _P]),
     "adct_t8_encode_zonal": (ctypes.c_int, [_PP, ctypes.c_int, _P, _PP, _I32, _P, _P]),
     "adct_t8_encode_quant": (ctypes.c_int, [_PP, ctypes.c_int, _P, _PP, _I32, _P, _P]),
+    "adct_mixed_encode": (ctypes.c_int, [_PP, ctypes.c_int, _I64, _P, _P, _PP, _I32, _P, _P]),
     "adct_recon": (ctypes.c_int, [_P, _PP, _P]),
     "adct_sse": (ctypes.c_int, [_PP, _PP, _I32, _P, _P]),
     "adct_fwd2d_quant": (ctypes.c_int, [_PP, ctypes.c_int, _P, _P]),
@@ -253,10 +254,13 @@ def zigzag_ranks() -> np.ndarray:
     return r.reshape(16, 16)
 
 
-def host_butterfly(x, inverse: bool = False, wht: bool = False) -> np.ndarray:
+def host_butterfly(x, inverse: bool = False, wht: bool = False, t8_halves: bool = False) -> np.ndarray:
     x = np.ascontiguousarray(np.asarray(x, dtype=np.int32).reshape(16))
     y = np.empty(16, np.int32)
-    which = 2 if wht else (1 if inverse else 0)
+    if t8_halves:
+        which = 4 if inverse else 3
+    else:
+        which = 2 if wht else (1 if inverse else 0)
     _check(_lib().adct_host_butterfly(which, x.ctypes.data, y.ctypes.data), "host_butterfly")
     return y
 
@@ -456,6 +460,21 @@ def t8_encode_quant(src, qp: int, dst, q=None, image_height=None, sse=None, want
     ih, sse, sp = _sse_out(src, image_height, sse, want_sse)
     _check(_lib().adct_t8_encode_quant(ctypes.byref(ps), qp, q.data_ptr() if q is not None else None,
                                        ctypes.byref(pd), ih, sp, _stream(stream)), "t8_encode_quant")
+    return sse
+
+
+MIXED_MAX_LAMBDA = 1 << 40
+
+
+def mixed_encode(src, qp: int, lam: int, dst, q=None, split=None, image_height=None, sse=None, want_sse=True,
+                 stream=None):
+    """Mixed 8/16-point codec: per 16x16 region the coding (one 16x16 block or
+    four 8x8 blocks) of lower D + lam * R; returns the per-image SSE."""
+    ps, pd = plane(src), plane(dst)
+    ih, sse, sp = _sse_out(src, image_height, sse, want_sse)
+    _check(_lib().adct_mixed_encode(ctypes.byref(ps), qp, lam, q.data_ptr() if q is not None else None,
+                                    split.data_ptr() if split is not None else None, ctypes.byref(pd), ih, sp,
+                                    _stream(stream)), "mixed_encode")
     return sse
 
 

@@ -6,6 +6,7 @@
 
 #include "adct.h"
 #include "adct_internal.hpp"
+#include "adct_t8_common.hpp"
 #include "adct_round.hpp"
 
 namespace adct {
@@ -178,10 +179,21 @@ int adct_work_queue(const int64_t* tiles_per_job, int32_t njobs, int32_t tiles_p
 // Host execution of the kernels' 1D butterflies (the same code the GPU
 // runs), for checking the dataflow without a GPU.
 int adct_host_butterfly(int32_t which, const int32_t* in16, int32_t* out16) {
-    if (!in16 || !out16 || which < 0 || which > 2) return ADCT_E_ARG;
+    if (!in16 || !out16 || which < 0 || which > 4) return ADCT_E_ARG;
     int32_t x[16], y[16];
     memcpy(x, in16, sizeof x);
-    if (which == 2)
+    if (which >= 3) {
+        // T8 or T8^T on each half, as the 8x8 and the mixed codecs apply it
+        for (int h = 0; h < 2; ++h) {
+            int32_t a[8], b[8];
+            memcpy(a, x + 8 * h, sizeof a);
+            if (which == 3)
+                fwd8(a, b);
+            else
+                inv8(a, b);
+            memcpy(y + 8 * h, b, sizeof b);
+        }
+    } else if (which == 2)
         wht16(x, y);
     else if (which == 1)
         inv16(x, y);

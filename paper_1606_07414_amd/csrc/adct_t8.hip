@@ -1,10 +1,6 @@
 // The 8-point approximation T8 on 8x8 blocks (the 8-point half of the
-// paper's second video scenario, Section 3.2).
-//
-// T8 is the sum-path block of the factorisation of Section 2.2: the even
-// rows of T act on the folded input x_j + x_{15-j} only, and their left
-// halves are T8 (T8[k][j] = T[2k][j]).  Its dataflow is the even path of the
-// 16-point one: 8 + 4 + 2 = 14 additions, no negations.
+// paper's second video scenario, Section 3.2).  T8's butterflies (14
+// additions) and quantiser factors are in adct_t8_common.hpp.
 //
 // One thread owns one 8x8 block, entirely in registers: the row pass, the
 // column pass, the retention or quantisation step, both inverse passes and
@@ -23,43 +19,11 @@
 #include <cmath>
 
 #include "adct_internal.hpp"
+#include "adct_t8_common.hpp"
 #include "adct_tile.hpp"
 
 namespace adct {
 namespace {
-
-// log2 d_k of T8's rows: d = (8, 2, 4, 2, 8, 2, 4, 2)
-__host__ __device__ constexpr int l8(int k) { return (k & 3) == 0 ? 3 : (k & 3) == 2 ? 2 : 1; }
-
-// X = T8 x (14 add/sub).
-template <typename V>
-__device__ __forceinline__ void fwd8(const V (&x)[8], V (&y)[8]) {
-    const V b0 = x[0] + x[7], b1 = x[1] + x[6], b2 = x[2] + x[5], b3 = x[3] + x[4];
-    y[1] = x[0] - x[7];
-    y[3] = x[5] - x[2];
-    y[5] = x[6] - x[1];
-    y[7] = x[4] - x[3];
-    const V c0 = b0 + b3, c1 = b1 + b2;
-    y[2] = b0 - b3;
-    y[6] = b2 - b1;
-    y[0] = c0 + c1;
-    y[4] = c0 - c1;
-}
-
-// x = T8^T y (the transposed dataflow, 14 add/sub).
-template <typename V>
-__device__ __forceinline__ void inv8(const V (&y)[8], V (&x)[8]) {
-    const V c0 = y[0] + y[4], c1 = y[0] - y[4];
-    const V b0 = c0 + y[2], b3 = c0 - y[2], b1 = c1 - y[6], b2 = c1 + y[6];
-    x[0] = b0 + y[1];
-    x[7] = b0 - y[1];
-    x[1] = b1 - y[5];
-    x[6] = b1 + y[5];
-    x[2] = b2 - y[3];
-    x[5] = b2 + y[3];
-    x[3] = b3 - y[7];
-    x[4] = b3 + y[7];
-}
 
 enum Op8 { kFwd8 = 0, kZonal8 = 1, kQuant8 = 2 };
 
@@ -370,19 +334,6 @@ int check_plane8(const adct_plane* p) {
 }
 
 int64_t blocks8(const adct_plane* p) { return (int64_t)(p->height / 8) * (p->width / 8); }
-
-double class_ss8(int c) { return 1.0 / std::sqrt((double)(1 << (c + 2))); }  // d_u d_v = 2^(c+2)
-
-bool quant_scales8(int qp, float* qs, float* dqs) {
-    if (qp < 0 || qp > 63) return false;
-    const double delta = exp2((qp - 4) / 6.0);
-    for (int c = 0; c < 5; ++c) {
-        const double ss = class_ss8(c);
-        if (qs) qs[c] = (float)(ss / delta);
-        if (dqs) dqs[c] = (float)(64.0 * delta * ss);
-    }
-    return true;
-}
 
 template <typename S, int OP, bool STORE>
 void launch8(const Args8& a, hipStream_t s) {

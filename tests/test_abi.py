@@ -310,5 +310,44 @@ def test_kernel_wht_butterfly_on_host():
     rng = np.random.default_rng(16)
     for x in rng.integers(-(1 << 20), 1 << 20, size=(5000, 16)):
         assert np.array_equal(adct.host_butterfly(x, wht=True), H @ x)
-    assert adct.lib().adct_host_butterfly(3, np.zeros(16, np.int32).ctypes.data,
+    assert adct.lib().adct_host_butterfly(5, np.zeros(16, np.int32).ctypes.data,
                                           np.zeros(16, np.int32).ctypes.data) == adct.E_ARG
+
+
+def test_kernel_t8_butterflies_on_host():
+    from oracle import t8 as E8
+    T8 = E8.transform_matrix_8()
+    rng = np.random.default_rng(1608)
+    for x in rng.integers(-(1 << 20), 1 << 20, size=(3000, 16)):
+        want = np.concatenate([T8 @ x[:8], T8 @ x[8:]])
+        assert np.array_equal(adct.host_butterfly(x, t8_halves=True), want)
+        want_t = np.concatenate([T8.T @ x[:8], T8.T @ x[8:]])
+        assert np.array_equal(adct.host_butterfly(x, inverse=True, t8_halves=True), want_t)
+    for k in range(16):
+        e = np.zeros(16, np.int32)
+        e[k] = 1
+        col = adct.host_butterfly(e, t8_halves=True)
+        assert np.array_equal(col[8 * (k // 8):8 * (k // 8) + 8], T8[:, k % 8])
+        assert not col[8 * (1 - k // 8):8 * (1 - k // 8) + 8].any()
+    assert adct.lib().adct_host_butterfly(5, FAKE, FAKE) == adct.E_ARG
+
+
+def test_mixed_argument_checks():
+    lib = adct.lib()
+    p = _plane(FAKE, adct.I16, 32, 48, 96)
+    u8 = _plane(FAKE, adct.U8, 32, 48, 48)
+    small = _plane(FAKE, adct.I16, 16, 48, 96)
+    f = lib.adct_mixed_encode
+    assert f(None, 27, 5, None, None, ctypes.byref(p), 32, None, None) == adct.E_ARG
+    assert f(ctypes.byref(p), 27, 5, None, None, ctypes.byref(u8), 32, None, None) == adct.E_SHAPE
+    assert f(ctypes.byref(p), 27, 5, None, None, ctypes.byref(small), 32, None, None) == adct.E_SHAPE
+    assert f(ctypes.byref(p), 27, -1, None, None, ctypes.byref(p), 32, None, None) == adct.E_ARG
+    assert f(ctypes.byref(p), 27, adct.MIXED_MAX_LAMBDA + 1, None, None, ctypes.byref(p), 32, None, None) == adct.E_ARG
+    assert f(ctypes.byref(p), 64, 5, None, None, ctypes.byref(p), 32, None, None) == adct.E_ARG
+    assert f(ctypes.byref(p), -1, 5, None, None, ctypes.byref(p), 32, None, None) == adct.E_ARG
+    assert f(ctypes.byref(p), 27, 5, FAKE + 8, None, ctypes.byref(p), 32, None, None) == adct.E_ALIGN
+    assert f(ctypes.byref(p), 27, 5, None, None, ctypes.byref(p), 24, FAKE, None) == adct.E_SHAPE
+    assert f(ctypes.byref(p), 27, 5, None, None, ctypes.byref(p), 0, FAKE, None) == adct.E_SHAPE
+    assert f(ctypes.byref(p), 27, 5, None, None, ctypes.byref(p), 32, FAKE + 4, None) == adct.E_ALIGN
+    bad = _plane(FAKE, adct.I16, 32, 40, 96)
+    assert f(ctypes.byref(bad), 27, 5, None, None, ctypes.byref(bad), 32, None, None) == adct.E_SHAPE
