@@ -176,11 +176,21 @@ def image_experiment(torch, adct, stream, x, coef, out, n_img):
     return res
 
 
+# int16 samples in, int16 levels and reconstruction out, one split flag
+MIXED_BYTES_PER_REGION = 512 + 512 + 512 + 1
+
+
+def mixed_lambda(qp: int) -> int:
+    """Lagrange multiplier of the mixed codec's size decision at `qp`: the
+    0.57 * 2^((QP - 12) / 3) of HEVC-style encoders, rounded to an integer."""
+    return int(round(0.57 * 2 ** ((qp - 12) / 3)))
+
+
 def video(torch, adct, stream, frames=64):
     """64 residual frames of 1920x1088 4:2:0 (Laplacian, scale 8): per QP the
     single-pass encoder (levels + reconstruction + per-frame SSE) and the
-    two-kernel path, over all three planes; and the same frames coded with
-    the 8-point transform on 8x8 blocks."""
+    two-kernel path, over all three planes; the same frames coded with the
+    8-point transform on 8x8 blocks; and with mixed 8/16-point coding."""
     import synth
     planes = [[], [], []]
     for f in range(frames):
@@ -193,6 +203,7 @@ def video(torch, adct, stream, frames=64):
     qs = [torch.empty((x.numel() // 256, 16, 16), dtype=torch.int16, device="cuda") for x in xs]
     sses = [torch.empty(frames, dtype=torch.int64, device="cuda") for _ in xs]
     q8s = [torch.empty((x.numel() // 64, 8, 8), dtype=torch.int16, device="cuda") for x in xs]
+    splits = [torch.empty(x.numel() // 256, dtype=torch.uint8, device="cuda") for x in xs]
     res = {"frames": frames, "tiles": tiles, "bytes_per_tile_fused": 1536, "bytes_per_block8_fused": 384, "qp": {}}
     for qp in (22, 27, 32, 37):
         def fused():
@@ -227,7 +238,29 @@ def video(torch, adct, stream, frames=64):
         res["qp"][qp]["t8"] = {"ms": ms8, "blocks8_per_s": 4 * tiles / (ms8 * 1e-3),
                                "gbs": 384 * 4 * tiles / (ms8 * 1e-3) / 1e9,
                                "psnr_yuv_6_1_1_db": float(np.mean((6 * psnr8[0] + psnr8[1] + psnr8[2]) / 8))}
+        # mixed 8/16-point coding (the second scenario with both transforms):
+        # per 16x16 region the coding of lower D + lambda R, lambda the usual
+        # Lagrange multiplier 0.57 * 2^((QP - 12) / 3) rounded, R the nonzero levels
+        lam = mixed_lambda(qp)
+
+        def mixed():
+            for x, o, q, sp, s, h in zip(xs, outs, qs, splits, sses, heights):
+                adct.mixed_encode(x, qp, lam, o, q=q, split=sp, image_height=h, sse=s, stream=stream)
+
+        msm = timed(torch, mixed, 10, stream)
+        mixed()
+        ssem = [s.cpu().numpy().astype(np.float64) for s in sses]
+        psnrm = [10 * np.log10(255.0 ** 2 * n / np.maximum(e, 1)) for e, n in zip(ssem, npix)]
+        nsplit = [int(sp.sum().item()) for sp in splits]
+        adds = sum((sp.numel() - k) * 2 * 16 * 44 + k * 4 * 2 * 8 * 14 for sp, k in zip(splits, nsplit))
+        res["qp"][qp]["mixed"] = {"lambda": lam, "ms": msm, "regions_per_s": tiles / (msm * 1e-3),
+                                  "gbs": MIXED_BYTES_PER_REGION * tiles / (msm * 1e-3) / 1e9,
+                                  "split_fraction": sum(nsplit) / tiles,
+                                  "split_fraction_y_u_v": [k / sp.numel() for sp, k in zip(splits, nsplit)],
+                                  "decoder_additions_per_sample": adds / (256 * tiles),
+                                  "psnr_yuv_6_1_1_db": float(np.mean((6 * psnrm[0] + psnrm[1] + psnrm[2]) / 8))}
     res["additions_per_sample_2d"] = {"t16": 2 * 44 / 16, "t8": 2 * 14 / 8}
+    res["bytes_per_region_mixed"] = MIXED_BYTES_PER_REGION
     return res
 
 
