@@ -18,9 +18,13 @@ namespace adct {
 // spacing.  So this equals (int32_t)roundf(x) for every x whose rounded value
 // fits an int32, in three instructions instead of seven.
 __host__ __device__ __forceinline__ int32_t round_away(float x) {
+    // The addition is its own rounding step: it must not absorb a multiply
+    // that produced x (a fused multiply-add would skip the rounding of the
+    // fp32 product that the quantiser definition applies first).
+#pragma clang fp contract(off)
     const float h = copysignf(0x1.fffffep-2f, x);
 #ifdef __HIP_DEVICE_COMPILE__
-    return (int32_t)__fadd_rn(x, h);
+    return (int32_t)(x + h);
 #else
     volatile float s = x + h;  // one fp32 addition, not fused or widened
     return (int32_t)s;

@@ -385,3 +385,84 @@ def test_sse_over_large_images_spread_and_split(h, w, n):
     q = adct.fwd2d_quant(xr, 32)
     s2 = host(adct.dequant_recon(q, 32, outr, ref=xr, image_height=h))
     assert np.array_equal(s2, s)
+
+
+# ---- the quantiser's fp32 product is rounded before the rounding step --------
+# A fused multiply-add of the product into the half-away rounding skips the
+# product's own fp32 rounding and changes some levels and dequantised values
+# (found by exhaustive search on the CPU).  These inputs land on such cases.
+_H = np.float32(np.nextafter(np.float32(0.5), np.float32(0)))
+
+
+def _fused_round(vals, factor):
+    """The multiply-add variant (one rounding of v * f + h), for choosing inputs."""
+    ex = np.asarray(vals, np.float64) * np.float64(np.float32(factor))
+    return np.trunc(np.float32(ex + np.where(ex < 0, -np.float64(_H), np.float64(_H)))).astype(np.int64)
+
+
+@pytest.mark.parametrize("qp,u,v", [(33, 0, 0), (36, 0, 3), (39, 0, 2), (42, 2, 3), (45, 2, 2)])
+def test_quant_product_rounded_before_rounding_step(qp, u, v):
+    # coefficient 35807 where the table entry is 0.0021923...
+    qs, _ = O.quant_tables(qp)
+    Y = np.zeros((2, 16, 16), np.int64)
+    Y[0, u, v], Y[1, u, v] = 35807, -35807
+    want = O.quantise(Y, qp)
+    assert want[0, u, v] != _fused_round([35807], qs[u, v])[0]  # the case matters
+    assert np.array_equal(host(adct.quant(dev(Y.astype(np.int32)), qp)), want)
+    if (u, v) == (0, 0):
+        # the same level through the single-pass encoder: a uint8 block of
+        # 255 samples of 140 and one of 107 has DC 35807
+        blk = np.full((16, 16), 140, np.uint8)
+        blk[15, 15] = 107
+        img = np.concatenate([blk, synth.ar1_image(qp, 16, 16)], axis=1)
+        x = dev(img)
+        out = torch.empty_like(x)
+        q = torch.zeros((2, 16, 16), dtype=torch.int16, device="cuda")
+        adct.encode_quant(x, qp, out, q=q)
+        assert np.array_equal(host(q), O.quantise(O.fwd2d(img), qp))
+
+
+@pytest.mark.parametrize("qp,u,v,levels", [
+    (0, 0, 3, [4224, -4224]), (0, 2, 3, [2112]), (27, 0, 0, [264, 6400]), (27, 0, 2, [132, 3200, -5376]),
+    (27, 2, 2, [66, 1600, -2688, 3712]), (27, 2, 3, [672, 1664]), (32, 0, 3, [2560]), (32, 2, 3, [-1280]),
+    (37, 0, 2, [5794, 5800]), (37, 2, 2, [2897, -2900]), (51, 2, 3, [42, 104, 272])])
+def test_dequant_product_rounded_before_rounding_step(qp, u, v, levels):
+    _, dqs = O.quant_tables(qp)
+    q = np.zeros((len(levels), 16, 16), np.int64)
+    q[:, u, v] = levels
+    want = O.dequantise(q, qp)
+    assert np.any(want[:, u, v] != _fused_round(levels, dqs[u, v]))  # the cases matter
+    assert np.array_equal(host(adct.dequant(dev(q.astype(np.int16)), qp)), want)
+
+
+@pytest.mark.parametrize("codec", ["encode_quant", "mixed"])
+def test_encoder_dequant_rounded_before_rounding_step(codec):
+    # a uint8 block of sum 60192 quantises its DC to 264 at QP 27, whose
+    # dequantised value the fused variant gets wrong by one; this seeded
+    # block (235 +- 12) is one where that changes reconstructed samples
+    _, dqs = O.quant_tables(27)
+    rng = np.random.default_rng(1)
+    blk = 235 + rng.integers(-12, 13, size=(16, 16))
+    blk[15, 15] += 60192 - blk.sum()
+    blk = blk.astype(np.uint8)
+    q = O.quantise(O.fwd2d(blk), 27)
+    assert q[0, 0, 0] == 264
+    z = O.dequantise(q, 27)
+    zf = z.copy()
+    nz = q != 0
+    zf[nz] = [_fused_round([lv], f)[0] for lv, f in zip(q[nz], np.broadcast_to(dqs, q.shape)[nz])]
+    r_sep = O.round_clamp(O.reconstruct_fixed(z), 0, 255)
+    assert not np.array_equal(r_sep, O.round_clamp(O.reconstruct_fixed(zf), 0, 255))  # the case matters
+    plane = np.concatenate([blk, synth.ar1_image(5, 16, 32)], axis=1)
+    x = dev(plane)
+    out = torch.empty_like(x)
+    if codec == "encode_quant":
+        s = host(adct.encode_quant(x, 27, out))
+        _, _, want = O.quant_reconstruct(plane, 27, 0, 255)
+    else:
+        from oracle import mixed as X
+        s = host(adct.mixed_encode(x, 27, 0, out))
+        split, _, want = X.mixed_encode(plane, 27, 0, 0, 255)
+        assert split[0] == 0  # the 16x16 coding is kept for this block
+    assert np.array_equal(host(out), want)
+    assert s[0] == O.sse(want, plane)
