@@ -425,8 +425,9 @@ int adct_autotune(int32_t op, int32_t param, const adct_job* jobs, int32_t njobs
  * (and fewer than max_inflight are held) and publishes each admitted request
  * to a persistent kernel through host-mapped memory.  One wave of that
  * kernel forwards new requests to its other workgroups, which claim work
- * items (runs of tiles of one request) as they appear and read the pixels in
- * place from the caller's pinned host memory (no copy ahead, no other
+ * items (runs of tiles of one request) as they appear, copy each item's
+ * pixel rows from the caller's pinned host memory into the pool in long
+ * contiguous runs and code them from there (no copy ahead, no other
  * stream), so requests that arrive while others run are coded alongside
  * them; the last workgroup to finish a request posts its SSE and a
  * completion flag to host memory.  In ADCT_SERVE_PLAIN mode the same
@@ -445,9 +446,8 @@ int adct_autotune(int32_t op, int32_t param, const adct_job* jobs, int32_t njobs
 #define ADCT_SERVE_PLAIN      1
 
 typedef struct adct_server_cfg {
-    int64_t pool_bytes;      /* device pool for request data: 3 bytes per pixel
-                                (persistent: levels, reconstruction), 4 (plain:
-                                also the copied source)                          */
+    int64_t pool_bytes;      /* device pool for request data: 4 bytes per pixel
+                                (the copied source, levels, reconstruction)      */
     int32_t qp;              /* quantiser for every request, [0, 63]            */
     int32_t mode;            /* ADCT_SERVE_PERSISTENT or ADCT_SERVE_PLAIN       */
     int32_t max_inflight;    /* admitted and not yet released, >= 1             */
@@ -500,8 +500,8 @@ int adct_server_create(adct_server** out, const adct_server_cfg* cfg);
 
 /* Queues one request.  host_pixels: uint8 [height][pitch_bytes] in host
  * memory, which must stay valid and unchanged until the request completes.
- * Persistent mode reads it in place: it must be pinned memory the device can
- * address (hipHostMalloc, or a pinned torch tensor), else ADCT_E_ARG, with
+ * Persistent mode reads it from the device: it must be pinned memory the
+ * device can address (hipHostMalloc, or a pinned torch tensor), else ADCT_E_ARG, with
  * host_pixels and pitch_bytes multiples of 16 (else ADCT_E_ALIGN).  Plain
  * mode copies it (pinned memory gives asynchronous copies).  arrival_ns < 0
  * means now; a later time holds the request back until then (open-loop

@@ -4,10 +4,12 @@
 // admitted, by a publication slot j (slots are handed out in admission order;
 // neither is ever reused within a server).
 //
-// Publication.  The loop reads each request's pixels in place from the
-// caller's pinned host memory (over the host link, fused with the first
-// pass), so nothing is copied ahead and no other stream is involved.  For
-// each admitted request the host thread writes its 128-byte descriptor into
+// Publication.  The loop takes each request's pixels straight from the
+// caller's pinned host memory: every work item first copies its own sample
+// rows over the host link into the request's pool block, in long contiguous
+// runs, and is then coded from there, so nothing is copied ahead, no other
+// stream is involved, and the transfer of one item overlaps the coding of
+// others.  For each admitted request the host thread writes its 128-byte descriptor into
 // slot j of a ring in host-mapped memory and then stores j + 1 to a
 // host-mapped slot count (release order).  Results (levels and
 // reconstruction) go to the request's block of the device pool.
@@ -54,8 +56,10 @@ struct ReqDesc {
     uint32_t bw, bw_m, bw_s1, bw_s2;          // 10-13: tiles per row and its FastDiv
     uint32_t ipb_m, ipb_s1, ipb_s2, nblk;     // 14-17: FastDiv by height / 16, tiles
     uint32_t req;                             // 18: request sequence number
-    uint32_t src_pitch;                       // 19: bytes between source rows
-    uint32_t pad[12];
+    uint32_t src_pitch;                       // 19: bytes between rows of src
+    uint64_t hsrc;                            // 20, 21: the caller's pinned pixels (device-visible)
+    uint32_t hsrc_pitch;                      // 22: bytes between their rows
+    uint32_t pad[9];
 };
 static_assert(sizeof(ReqDesc) == 128, "one descriptor per 128-byte line");
 
@@ -100,6 +104,44 @@ __device__ __forceinline__ uint64_t rfl64(uint64_t v) {
 }
 
 constexpr int kServeTPW = 16;
+
+// Copies the samples of tiles t0 .. t1-1 (raster order over tile rows of
+// width bw) of a uint8 image from the caller's pinned host memory to its
+// copy in device memory, so that the item is then coded from device memory.
+// Per tile row the item covers one run of tiles, so each of its 16 sample
+// rows is one contiguous segment; lanes take consecutive 64-byte pieces of
+// the segments.  Reads of host memory over the bus reach the link's rate
+// only in long contiguous runs like these (the coding's own access, 16 bytes
+// of each of 16 tiles per sample row, reaches about three quarters of it).
+// The caller's barrier then makes the copy visible to the whole workgroup:
+// every address the item reads afterwards is one this workgroup wrote.
+__device__ __forceinline__ void stage_item(const char* __restrict__ hsrc, uint32_t hpitch, char* __restrict__ dsrc,
+                                           uint32_t dpitch, uint32_t bw, const FastDiv& bwdiv, uint32_t t0,
+                                           uint32_t t1) {
+    for (uint32_t t = t0; t < t1;) {
+        const uint32_t by = fdiv(t, bwdiv), bx0 = t - by * bw;
+        const uint32_t bx1 = min(bw, bx0 + (t1 - t));
+        const uint32_t len = (bx1 - bx0) * 16u;     // bytes of each sample row
+        const uint32_t per_row = (len + 63u) / 64u;  // 64-byte pieces per row
+        for (uint32_t c = threadIdx.x; c < 16u * per_row; c += blockDim.x) {
+            const uint32_t r = c / per_row, k = c - r * per_row;
+            const uint32_t off = bx0 * 16u + k * 64u;
+            const uint32_t n = min(4u, (len - k * 64u) / 16u);  // 16-byte words in this piece
+            const uint4* hp = reinterpret_cast<const uint4*>(hsrc + (int64_t)(by * 16u + r) * hpitch + off);
+            uint4* dp = reinterpret_cast<uint4*>(dsrc + (int64_t)(by * 16u + r) * dpitch + off);
+            if (n == 4) {
+                const uint4 v0 = hp[0], v1 = hp[1], v2 = hp[2], v3 = hp[3];
+                dp[0] = v0;
+                dp[1] = v1;
+                dp[2] = v2;
+                dp[3] = v3;
+            } else {
+                for (uint32_t i = 0; i < n; ++i) dp[i] = hp[i];
+            }
+        }
+        t += bx1 - bx0;
+    }
+}
 using ServeMode = Mode<kInSamples, kStoreQ, kMidQuant, kOutSamples, -1, true>;
 
 // Group arguments of slot j from its descriptor words (held in LDS).
@@ -212,11 +254,16 @@ __global__ __launch_bounds__(kServeTPW * 8) void k_serve(ServeArgs s) {
             __syncthreads();
             cur = j;
         }
-        const GroupArgs a = args_from_desc(sh_desc, s, j);
         const uint32_t* dw = reinterpret_cast<const uint32_t*>(sh_desc);
         const uint32_t nitems = rfl(dw[8]), tpi = rfl(dw[9]), nblk = rfl(dw[17]), req = rfl(dw[18]);
         const uint32_t t0 = g * tpi;
         const uint32_t gend = min(nblk, t0 + tpi);
+        // the item's samples into the pool first (before the group arguments
+        // are formed, which keeps fewer scalar values live across the copy)
+        stage_item(global_ptr(rfl64(sh_desc[10])), rfl(dw[22]), global_ptr(rfl64(sh_desc[0])), rfl(dw[19]),
+                   rfl(dw[10]), FastDiv{rfl(dw[11]), rfl(dw[12]), rfl(dw[13])}, t0, gend);
+        __syncthreads();
+        const GroupArgs a = args_from_desc(sh_desc, s, j);
         SseAcc acc{0, kNoImage};
         RowWords rows;
         uint32_t g0 = t0;
@@ -266,9 +313,8 @@ struct Req {
     int ev = -1;  // plain: event slot marking the end of the request
 };
 
-// Pool block of a request: persistent mode keeps reconstruction and levels
-// (3 bytes per pixel); plain mode also keeps the copied source in front of
-// them (4 bytes per pixel).
+// Pool block of a request: the copied source, the reconstruction and the
+// levels (4 bytes per pixel).
 struct Block {
     char *src, *dst, *q;
 };
@@ -377,8 +423,8 @@ Block block_of(const adct_server* S, const Req& r) {
     const int64_t plane = Pool::round_up((int64_t)r.h * r.w);
     char* base = S->pool_mem + r.off;
     Block b;
-    b.src = S->cfg.mode == ADCT_SERVE_PLAIN ? base : nullptr;
-    b.dst = S->cfg.mode == ADCT_SERVE_PLAIN ? base + plane : base;
+    b.src = base;
+    b.dst = base + plane;
     b.q = b.dst + plane;
     return b;
 }
@@ -394,9 +440,9 @@ int64_t item_tiles(int32_t cfg_tiles_per_item, int64_t tiles) {
     return t;
 }
 
-int64_t block_bytes(int32_t mode, int32_t h, int32_t w) {
+int64_t block_bytes(int32_t h, int32_t w) {
     const int64_t plane = (int64_t)h * w;
-    return (mode == ADCT_SERVE_PLAIN ? 2 : 1) * Pool::round_up(plane) + 2 * plane;
+    return 2 * Pool::round_up(plane) + 2 * plane;
 }
 
 // Hands an admitted request to the device (called with mu held).  Persistent
@@ -426,12 +472,14 @@ void issue(adct_server* S, int64_t k) {
     } else {
         ReqDesc d;
         memset(&d, 0, sizeof d);
-        d.src = r.dev_src;
+        d.src = (uint64_t)(uintptr_t)b.src;
+        d.hsrc = r.dev_src;
+        d.hsrc_pitch = (uint32_t)r.pitch;
         d.dst = (uint64_t)(uintptr_t)b.dst;
         d.q = (uint64_t)(uintptr_t)b.q;
         d.height = (uint32_t)r.h;
         d.width = (uint32_t)r.w;
-        d.src_pitch = (uint32_t)r.pitch;
+        d.src_pitch = (uint32_t)r.w;
         d.nblk = (uint32_t)r.tiles;
         const int64_t tpi = item_tiles(S->cfg.tiles_per_item, r.tiles);
         d.tiles_per_item = (uint32_t)tpi;
@@ -662,8 +710,8 @@ int adct_server_submit(adct_server* S, const void* host_pixels, int32_t height, 
     r.w = width;
     r.pitch = pitch_bytes;
     if (S->cfg.mode == ADCT_SERVE_PERSISTENT) {
-        // the loop reads the pixels in place: they must be in pinned host
-        // memory that the device can address, 16-byte aligned rows
+        // the loop reads the pixels from the caller's memory: it must be
+        // pinned host memory that the device can address, 16-byte aligned rows
         if (((uintptr_t)host_pixels & 15) || (pitch_bytes & 15) || pitch_bytes > 0xffffffffll) return ADCT_E_ALIGN;
         hipPointerAttribute_t attr;
         memset(&attr, 0, sizeof attr);
@@ -672,7 +720,7 @@ int adct_server_submit(adct_server* S, const void* host_pixels, int32_t height, 
         if (e != hipSuccess || attr.type != hipMemoryTypeHost || !attr.devicePointer) return ADCT_E_ARG;
         r.dev_src = (uint64_t)(uintptr_t)attr.devicePointer;
     }
-    r.bytes = block_bytes(S->cfg.mode, height, width);
+    r.bytes = block_bytes(height, width);
     r.tiles = (int64_t)height * width / 256;
     r.t_arrival = arrival_ns < 0 ? clock_ns() : arrival_ns;
     std::lock_guard<std::mutex> lk(S->mu);
