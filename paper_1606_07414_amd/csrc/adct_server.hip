@@ -78,6 +78,10 @@ struct ServeArgs {
     uint32_t* quit;              // epoch of the launch told to end
     uint32_t* claim;             // per slot: items handed out (may overshoot)
     uint32_t* done;              // per slot: items finished
+    uint32_t* staged;            // per slot: items whose samples are in the pool
+    uint32_t* stage_low;         // every slot below this has all its samples in the pool
+    uint32_t* stage_next;        // staging tickets handed out
+    uint32_t* stage_done;        // staging tickets finished
     unsigned long long* sse;     // per slot: SSE accumulator
     Completion* comp;            // per request, host-mapped
     const uint32_t* stop;        // host-mapped
@@ -104,6 +108,14 @@ __device__ __forceinline__ uint64_t rfl64(uint64_t v) {
 }
 
 constexpr int kServeTPW = 16;
+
+#ifndef ADCT_SERVE_STAGERS
+#define ADCT_SERVE_STAGERS 64
+#endif
+// Workgroups that copy samples over the host link at one time.  Enough to
+// keep the link busy (each has 8 KB of reads in flight), few enough that its
+// queue stays short for the loop's own polls of host memory.
+constexpr uint32_t kStagers = ADCT_SERVE_STAGERS;
 
 // Copies the samples of tiles t0 .. t1-1 (raster order over tile rows of
 // width bw) of a uint8 image from the caller's pinned host memory to its
@@ -258,11 +270,28 @@ __global__ __launch_bounds__(kServeTPW * 8) void k_serve(ServeArgs s) {
         const uint32_t nitems = rfl(dw[8]), tpi = rfl(dw[9]), nblk = rfl(dw[17]), req = rfl(dw[18]);
         const uint32_t t0 = g * tpi;
         const uint32_t gend = min(nblk, t0 + tpi);
+        // The host link serves requests in order: an item is staged once
+        // every earlier request has all its samples in the pool, so a later
+        // request does not take link bandwidth from an earlier one (coding
+        // still overlaps the next request's transfer).  Claims go in slot
+        // order, so the items of earlier slots are all held by workers that
+        // are not waiting here: the lowest such slot always progresses.
+        // At most kStagers items are staged at one time (tickets in order).
+        if (tid == 0) {
+            while (load_sys(s.stage_low) < j) __builtin_amdgcn_s_sleep(2);
+            const uint32_t ticket = atomicAdd(s.stage_next, 1u);
+            while (load_sys(s.stage_done) + kStagers <= ticket) __builtin_amdgcn_s_sleep(1);
+        }
+        __syncthreads();
         // the item's samples into the pool first (before the group arguments
         // are formed, which keeps fewer scalar values live across the copy)
         stage_item(global_ptr(rfl64(sh_desc[10])), rfl(dw[22]), global_ptr(rfl64(sh_desc[0])), rfl(dw[19]),
                    rfl(dw[10]), FastDiv{rfl(dw[11]), rfl(dw[12]), rfl(dw[13])}, t0, gend);
         __syncthreads();
+        if (tid == 0) {
+            atomicAdd(s.stage_done, 1u);
+            if (atomicAdd(s.staged + j, 1u) + 1u == nitems) atomicMax(s.stage_low, j + 1u);
+        }
         const GroupArgs a = args_from_desc(sh_desc, s, j);
         SseAcc acc{0, kNoImage};
         RowWords rows;
@@ -358,7 +387,7 @@ struct adct_server {
     uint32_t* h_count = nullptr;      // host-mapped slot count
     uint32_t* d_hcount = nullptr;
     ReqDesc* d_desc = nullptr;        // device copy of the ring
-    uint32_t* d_state = nullptr;      // count, low, quit, then claim[n], done[n]
+    uint32_t* d_state = nullptr;      // count, low, quit, stage_low, stage_next, stage_done, then claim[n], done[n], staged[n]
     unsigned long long* d_sse = nullptr;
     Completion* h_comp = nullptr;     // host-mapped, by request
     Completion* d_comp = nullptr;     // its device address
@@ -372,8 +401,12 @@ namespace {
 uint32_t* st_count(adct_server* S) { return S->d_state; }
 uint32_t* st_low(adct_server* S) { return S->d_state + 32; }
 uint32_t* st_quit(adct_server* S) { return S->d_state + 64; }
-uint32_t* st_claim(adct_server* S) { return S->d_state + 96; }
-uint32_t* st_done(adct_server* S) { return S->d_state + 96 + S->cfg.max_requests; }
+uint32_t* st_stage_low(adct_server* S) { return S->d_state + 96; }
+uint32_t* st_stage_next(adct_server* S) { return S->d_state + 128; }
+uint32_t* st_stage_done(adct_server* S) { return S->d_state + 160; }
+uint32_t* st_claim(adct_server* S) { return S->d_state + 192; }
+uint32_t* st_done(adct_server* S) { return S->d_state + 192 + S->cfg.max_requests; }
+uint32_t* st_staged(adct_server* S) { return S->d_state + 192 + 2 * S->cfg.max_requests; }
 
 bool hip_ok(adct_server* S, hipError_t e) {
     if (e != hipSuccess && !S->hip_error) S->hip_error = (int)e;
@@ -390,6 +423,10 @@ void launch_loop(adct_server* S) {
     a.quit = st_quit(S);
     a.claim = st_claim(S);
     a.done = st_done(S);
+    a.staged = st_staged(S);
+    a.stage_low = st_stage_low(S);
+    a.stage_next = st_stage_next(S);
+    a.stage_done = st_stage_done(S);
     a.sse = S->d_sse;
     a.comp = S->d_comp;
     a.stop = S->d_stop;
@@ -674,7 +711,7 @@ int adct_server_create(adct_server** out, const adct_server_cfg* cfg_in) {
              hipHostGetDevicePointer(reinterpret_cast<void**>(&S->d_stop), S->h_stop, 0) == hipSuccess;
     }
     if (ok && cfg.mode == ADCT_SERVE_PERSISTENT) {
-        const size_t state_words = 96 + 2 * n;
+        const size_t state_words = 192 + 3 * n;
         ok = hipMalloc(reinterpret_cast<void**>(&S->d_desc), n * sizeof(ReqDesc)) == hipSuccess &&
              hipMalloc(reinterpret_cast<void**>(&S->d_state), state_words * sizeof(uint32_t)) == hipSuccess &&
              hipMemset(S->d_state, 0, state_words * sizeof(uint32_t)) == hipSuccess &&
