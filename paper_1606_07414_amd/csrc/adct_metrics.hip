@@ -4,10 +4,17 @@
 // Per image: local statistics under an 11x11 Gaussian window (standard
 // deviation 1.5, unit sum) at every position where the window lies inside
 // the image, SSIM at each such position, and their mean.  The window is
-// separable, so a workgroup computes a 16x16 tile of positions from a 26x26
-// patch of both images: a horizontal pass (five weighted sums: x, y, x^2, y^2,
-// xy) over 26 rows into LDS, then a vertical pass per position.  Everything
-// is in float64: the variances are differences of nearly equal moments.
+// separable.  A workgroup computes a tile of 16 x 48 positions from a
+// 26 x 58 patch of both images (loaded as aligned 16-byte words):
+//   horizontal pass: each thread takes one patch row and four adjacent
+//     positions, holding the 14 samples they need in registers; the window
+//     is symmetric, so the five weighted sums (x, y, x^2, y^2, xy) are
+//     formed from exact integer sums of sample pairs, six multiply-adds
+//     each in float64, and go to LDS;
+//   vertical pass: each thread takes three positions of one column, reading
+//     the 13 rows they need once per quantity.
+// Everything after the integer pair sums is float64: the variances are
+// differences of nearly equal moments.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -17,9 +24,19 @@
 namespace adct {
 namespace {
 
-constexpr int kWin = 11;             // window side
-constexpr int kOut = 16;             // positions per tile side
-constexpr int kPatch = kOut + kWin - 1;  // 26
+constexpr int kWin = 11;                  // window side
+constexpr int kTW = 16;                   // positions per tile row
+#ifndef ADCT_SSIM_TH
+#define ADCT_SSIM_TH 48
+#endif
+constexpr int kTH = ADCT_SSIM_TH;         // positions per tile column
+constexpr int kPW = kTW + kWin - 1;       // 26: patch width
+constexpr int kPH = kTH + kWin - 1;       // 58: patch height
+constexpr int kHW = 4;                    // positions per thread, horizontal pass
+constexpr int kVH = kTH / 16;             // positions per thread, vertical pass
+constexpr int kLdh = kTW;                 // LDS row stride of the horizontal sums (doubles)
+static_assert(kTH % 16 == 0 && (kTH / kVH) * kTW == 256, "one vertical work item per thread");
+static_assert(kPW <= 32, "a patch row fits two 16-byte words");
 
 struct SsimArgs {
     const uint8_t* a;
@@ -39,64 +56,103 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
     return v;
 }
 
+// 40 KB of LDS and at most 128 VGPRs: four workgroups per CU.
 __global__ __launch_bounds__(256) void k_ssim(SsimArgs s) {
-    __shared__ float pa[kPatch][kPatch + 1], pb[kPatch][kPatch + 1];
-    __shared__ double h[5][kPatch][kOut];
+    __shared__ uint4 pa[kPH][2], pb[kPH][2];  // patch rows as two 16-byte words (26 of 32 bytes used)
+    __shared__ double h[5][kPH][kLdh];
     __shared__ double red[4];
     const int tid = threadIdx.x;
     const uint32_t per_image = s.tiles_x * s.tiles_y;
     const uint32_t valid_h = s.image_height - (kWin - 1), valid_w = s.width - (kWin - 1);
     for (uint64_t unit = blockIdx.x; unit < s.units; unit += gridDim.x) {
         const uint32_t img = (uint32_t)(unit / per_image), rem = (uint32_t)(unit % per_image);
-        const uint32_t oy = (rem / s.tiles_x) * kOut, ox = (rem % s.tiles_x) * kOut;
+        const uint32_t oy = (rem / s.tiles_x) * kTH, ox = (rem % s.tiles_x) * kTW;
         __syncthreads();  // the previous tile is done with LDS
-        for (int t = tid; t < kPatch * kPatch; t += 256) {
-            const int i = t / kPatch, j = t % kPatch;
-            const uint32_t y = oy + (uint32_t)i, x = ox + (uint32_t)j;
-            float va = 0.f, vb = 0.f;
-            if (y < s.image_height && x < s.width) {  // outside: feeds only positions that are not used
+        for (int t = tid; t < 4 * kPH; t += 256) {
+            // one 16-byte word per step: row i, word k of image a or b.  ox
+            // and the width are multiples of 16, so a word lies entirely
+            // inside or outside the image; outside it feeds only positions
+            // that are not used.
+            const int i = t >> 2, k = t & 1, im = (t >> 1) & 1;
+            const uint32_t y = oy + (uint32_t)i, x = ox + 16u * (uint32_t)k;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (y < s.image_height && x < s.width) {
                 const int64_t row = (int64_t)img * s.image_height + y;
-                va = (float)s.a[row * s.pitch_a + x];
-                vb = (float)s.b[row * s.pitch_b + x];
+                v = im ? *reinterpret_cast<const uint4*>(s.b + row * s.pitch_b + x)
+                       : *reinterpret_cast<const uint4*>(s.a + row * s.pitch_a + x);
             }
-            pa[i][j] = va;
-            pb[i][j] = vb;
+            (im ? pb : pa)[i][k] = v;
         }
         __syncthreads();
-        for (int t = tid; t < kPatch * kOut; t += 256) {
-            const int i = t / kOut, j = t % kOut;
-            double sa = 0, sb = 0, saa = 0, sbb = 0, sab = 0;
+        for (int hw = tid; hw < kPH * (kTW / kHW); hw += 256) {
+            // horizontal pass: patch row r, positions j0 .. j0 + 3
+            const int r = hw / (kTW / kHW), j0 = (hw % (kTW / kHW)) * kHW;
+            int32_t xa[kHW + kWin - 1], xb[kHW + kWin - 1];
+            const uint8_t* ra = reinterpret_cast<const uint8_t*>(pa[r]);
+            const uint8_t* rb = reinterpret_cast<const uint8_t*>(pb[r]);
 #pragma unroll
-            for (int k = 0; k < kWin; ++k) {
-                const double xa = pa[i][j + k], xb = pb[i][j + k], w = s.w[k];
-                sa = fma(w, xa, sa);
-                sb = fma(w, xb, sb);
-                saa = fma(w, xa * xa, saa);
-                sbb = fma(w, xb * xb, sbb);
-                sab = fma(w, xa * xb, sab);
+            for (int c = 0; c < kHW + kWin - 1; ++c) {
+                xa[c] = ra[j0 + c];
+                xb[c] = rb[j0 + c];
             }
-            h[0][i][j] = sa;
-            h[1][i][j] = sb;
-            h[2][i][j] = saa;
-            h[3][i][j] = sbb;
-            h[4][i][j] = sab;
+#pragma unroll
+            for (int m = 0; m < kHW; ++m) {
+                double acc[5];
+                // centre tap
+                {
+                    const int32_t a = xa[m + 5], b = xb[m + 5];
+                    const double w = s.w[5];
+                    acc[0] = w * (double)a;
+                    acc[1] = w * (double)b;
+                    acc[2] = w * (double)(a * a);
+                    acc[3] = w * (double)(b * b);
+                    acc[4] = w * (double)(a * b);
+                }
+                // taps k and 10 - k share a weight: exact integer pair sums
+#pragma unroll
+                for (int k = 0; k < 5; ++k) {
+                    const int32_t a0 = xa[m + k], a1 = xa[m + kWin - 1 - k];
+                    const int32_t b0 = xb[m + k], b1 = xb[m + kWin - 1 - k];
+                    const double w = s.w[k];
+                    acc[0] = fma(w, (double)(a0 + a1), acc[0]);
+                    acc[1] = fma(w, (double)(b0 + b1), acc[1]);
+                    acc[2] = fma(w, (double)(a0 * a0 + a1 * a1), acc[2]);
+                    acc[3] = fma(w, (double)(b0 * b0 + b1 * b1), acc[3]);
+                    acc[4] = fma(w, (double)(a0 * b0 + a1 * b1), acc[4]);
+                }
+#pragma unroll
+                for (int q = 0; q < 5; ++q) h[q][r][j0 + m] = acc[q];
+                // keeps the four positions' work from being interleaved (registers)
+                __builtin_amdgcn_sched_barrier(0);
+            }
         }
         __syncthreads();
-        const int i = tid / kOut, j = tid % kOut;
+        // vertical pass: column j, positions i0 .. i0 + 2
+        const int j = tid % kTW, i0 = (tid / kTW) * kVH;
+        double st[5][kVH];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            double col[kVH + kWin - 1];
+#pragma unroll
+            for (int c = 0; c < kVH + kWin - 1; ++c) col[c] = h[q][i0 + c][j];
+#pragma unroll
+            for (int m = 0; m < kVH; ++m) {
+                double v = s.w[0] * col[m];
+#pragma unroll
+                for (int k = 1; k < kWin; ++k) v = fma(s.w[k], col[m + k], v);
+                st[q][m] = v;
+            }
+            // one quantity's column at a time (registers)
+            __builtin_amdgcn_sched_barrier(0);
+        }
         double v = 0.0;
-        if (oy + (uint32_t)i < valid_h && ox + (uint32_t)j < valid_w) {
-            double ma = 0, mb = 0, eaa = 0, ebb = 0, eab = 0;
 #pragma unroll
-            for (int k = 0; k < kWin; ++k) {
-                const double w = s.w[k];
-                ma = fma(w, h[0][i + k][j], ma);
-                mb = fma(w, h[1][i + k][j], mb);
-                eaa = fma(w, h[2][i + k][j], eaa);
-                ebb = fma(w, h[3][i + k][j], ebb);
-                eab = fma(w, h[4][i + k][j], eab);
+        for (int m = 0; m < kVH; ++m) {
+            if (oy + (uint32_t)(i0 + m) < valid_h && ox + (uint32_t)j < valid_w) {
+                const double ma = st[0][m], mb = st[1][m];
+                const double vaa = st[2][m] - ma * ma, vbb = st[3][m] - mb * mb, cab = st[4][m] - ma * mb;
+                v += ((2.0 * ma * mb + s.c1) * (2.0 * cab + s.c2)) / ((ma * ma + mb * mb + s.c1) * (vaa + vbb + s.c2));
             }
-            const double vaa = eaa - ma * ma, vbb = ebb - mb * mb, cab = eab - ma * mb;
-            v = ((2.0 * ma * mb + s.c1) * (2.0 * cab + s.c2)) / ((ma * ma + mb * mb + s.c1) * (vaa + vbb + s.c2));
         }
         v = wave_sum_f64(v);
         if ((tid & 63) == 0) red[tid >> 6] = v;
@@ -143,8 +199,8 @@ int adct_ssim(const adct_plane* a, const adct_plane* b, int32_t image_height, do
     s.width = (uint32_t)a->width;
     s.image_height = (uint32_t)image_height;
     const uint32_t vh = s.image_height - (kWin - 1), vw = s.width - (kWin - 1);
-    s.tiles_x = (vw + kOut - 1) / kOut;
-    s.tiles_y = (vh + kOut - 1) / kOut;
+    s.tiles_x = (vw + kTW - 1) / kTW;
+    s.tiles_y = (vh + kTH - 1) / kTH;
     s.units = (uint64_t)nimg * s.tiles_x * s.tiles_y;
     double g[kWin], gs = 0.0;
     for (int k = 0; k < kWin; ++k) {
