@@ -364,10 +364,35 @@ def cpu_baseline(img: np.ndarray):
         passes += 1
     dt = time.perf_counter() - t0
     tiles = (H // 16) * (SIDE // 16) * len(RS) * passes
-    return {"value": tiles / dt, "unit": "16x16 blocks/s", "cores": oracle_c.threads(), "kind": "oracle",
-            "sample": f"the full workload ({H // SIDE} images, fwd + zonal inverse + SSE at each r in "
-                      f"{list(RS)}) x {passes} pass(es), C oracle (dense int64 16x16 products, OpenMP), "
-                      f"{dt:.1f} s"}
+    cores = oracle_c.threads()
+    out = {"value": tiles / dt, "unit": "16x16 blocks/s", "cores": cores, "kind": "oracle",
+           "sample": f"the full workload ({H // SIDE} images, fwd + zonal inverse + SSE at each r in "
+                     f"{list(RS)}) x {passes} pass(es), C oracle (dense int64 16x16 products, OpenMP), "
+                     f"{dt:.1f} s"}
+    # the same C oracle on one thread, and the numpy oracle, on smaller samples
+    n1 = 64
+    sub = img[:n1 * SIDE]
+    oracle_c.set_threads(1)
+    t1 = time.perf_counter()
+    for r in RS:
+        coef = oracle_c.fwd2d_u8(sub)
+        oracle_c.zonal_recon_u8(coef, n1 * SIDE, SIDE, r, sub, SIDE)
+    d1 = time.perf_counter() - t1
+    oracle_c.set_threads(cores)
+    out["single_thread"] = {"value": n1 * 1024 * len(RS) / d1, "cores": 1,
+                            "sample": f"{n1} images x every r, {d1:.1f} s"}
+    from oracle import adct_oracle as O
+    n2 = 4
+    sub = img[:n2 * SIDE]
+    t2 = time.perf_counter()
+    for r in RS:
+        R = O.reconstruct_fixed(O.zonal(O.fwd2d(sub), r))
+        rec = O.from_tiles(O.round_clamp(R, 0, 255), n2 * SIDE, SIDE)
+        O.sse(rec, sub)
+    d2 = time.perf_counter() - t2
+    out["numpy_oracle"] = {"value": n2 * 1024 * len(RS) / d2,
+                           "sample": f"{n2} images x every r, numpy int64 (einsum), {d2:.1f} s"}
+    return out
 
 
 def main():

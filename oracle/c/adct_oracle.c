@@ -47,6 +47,15 @@ int oracle_threads(void) {
 #endif
 }
 
+/* Threads of the following calls (timing at one thread and at all). */
+void oracle_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* coef[k][u][v] = sum_i sum_j T[u][i] A_k[i][j] T[v][j], raster block order. */
 void oracle_fwd2d_u8(const uint8_t* img, int64_t H, int64_t W, int64_t pitch, int64_t* coef) {
     const int64_t bw = W / 16, nblk = (H / 16) * bw;

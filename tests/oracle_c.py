@@ -21,6 +21,7 @@ def load():
         P = ctypes.c_void_p
         I64 = ctypes.c_int64
         lib.oracle_threads.restype = ctypes.c_int
+        lib.oracle_set_threads.argtypes = [ctypes.c_int]
         lib.oracle_fwd2d_u8.argtypes = [P, I64, I64, I64, P]
         lib.oracle_zonal_recon_u8.argtypes = [P, I64, I64, ctypes.c_int, P, I64, P, I64, P]
         _lib = lib
@@ -29,6 +30,10 @@ def load():
 
 def threads() -> int:
     return load().oracle_threads()
+
+
+def set_threads(n: int) -> None:
+    load().oracle_set_threads(n)
 
 
 def fwd2d_u8(img: np.ndarray) -> np.ndarray:
