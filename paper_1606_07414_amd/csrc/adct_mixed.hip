@@ -137,13 +137,16 @@ struct Coded {
     int32_t d, r;     // the lane's share of D (its row) and R (its column)
 };
 
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+
 // One coding of the wave's four regions.  Lane (g, i): x is row i of region
-// slot g; on return the lane holds column i's levels, row i's reconstruction
-// and its shares of D and R.  fq / fd are the lane's quantiser / dequantiser
-// factors for column i, indexed by row_class(u).
+// slot g (xw the same samples as 16-bit pairs); on return the lane holds
+// column i's levels, row i's reconstruction and its shares of D and R.  fq /
+// fd are the lane's quantiser / dequantiser factors for column i, indexed by
+// row_class(u).
 template <typename S, bool EIGHT>
-__device__ __forceinline__ void code(const int32_t (&x)[16], int32_t* t, int i, const float (&fq)[3],
-                                     const float (&fd)[3], Coded& c) {
+__device__ __forceinline__ void code(const int32_t (&x)[16], const uint32_t (&xw)[8], int32_t* t, int i,
+                                     const float (&fq)[3], const float (&fd)[3], Coded& c) {
     constexpr int kBits = EIGHT ? 6 : 8;
     int32_t a[16], b[16];
     fwd_line<EIGHT>(x, a);  // row pass
@@ -182,15 +185,19 @@ __device__ __forceinline__ void code(const int32_t (&x)[16], int32_t* t, int i, 
     constexpr int32_t lo = Samples<S>::kLo, hi = Samples<S>::kHi;
     c.d = 0;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
+    for (int m = 0; m < 8; ++m) {
         // clamp before the shift: floor((R + half) / 2^bits) lands in [lo, hi]
-        const int32_t o = clamp_i32(b[j], lo * (1 << kBits), hi * (1 << kBits) + (1 << kBits) - 1) >> kBits;
-        const int32_t e = o - x[j];
-        c.d += e * e;
-        if (j & 1)
-            c.out[j >> 1] |= (uint32_t)o << 16;
+        const int32_t r0 = clamp_i32(b[2 * m], lo * (1 << kBits), hi * (1 << kBits) + (1 << kBits) - 1);
+        const int32_t r1 = clamp_i32(b[2 * m + 1], lo * (1 << kBits), hi * (1 << kBits) + (1 << kBits) - 1);
+        uint32_t w;
+        if constexpr (kBits == 8)
+            w = __builtin_amdgcn_perm((uint32_t)r1, (uint32_t)r0, 0x06050201u);  // bytes 1-2 of each: R >> 8
         else
-            c.out[j >> 1] = (uint32_t)o & 0xffffu;
+            w = ((uint32_t)(r0 >> kBits) & 0xffffu) | ((uint32_t)(r1 >> kBits) << 16);
+        c.out[m] = w;
+        // the two errors as 16-bit lanes, squared and summed by one dot product
+        const s16x2 e = __builtin_bit_cast(s16x2, w) - __builtin_bit_cast(s16x2, xw[m]);
+        c.d = __builtin_amdgcn_sdot2(e, e, c.d, false);
     }
 }
 
@@ -233,9 +240,12 @@ __global__ __launch_bounds__(256) void k_mixed(MixArgs a) {
         const int64_t row = (int64_t)(by * 16u + (uint32_t)i);
         int32_t x[16];
         Samples<S>::load(a.src + row * a.src_pitch + (int64_t)bx * 16 * (int64_t)sizeof(S), x);
+        uint32_t xw[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) xw[m] = __builtin_amdgcn_perm((uint32_t)x[2 * m + 1], (uint32_t)x[2 * m], 0x05040100u);
         Coded c16, c8;
-        code<S, false>(x, t, i, fq16, fd16, c16);
-        code<S, true>(x, t, i, fq8, fd8, c8);
+        code<S, false>(x, xw, t, i, fq16, fd16, c16);
+        code<S, true>(x, xw, t, i, fq8, fd8, c8);
         const int32_t d16 = region_sum(c16.d), d8 = region_sum(c8.d);
         const int32_t rr = region_sum(c16.r | (c8.r << 16));
         const long long j16 = (long long)d16 + a.lambda * (long long)(rr & 0xffff);
