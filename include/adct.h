@@ -79,6 +79,12 @@ const char* adct_strerror(int code);
 /* ADCT_ABI_VERSION of the loaded library. */
 int adct_abi_version(void);
 
+/* Waits for the work queued on `stream` and reports whether it, or an
+ * earlier HIP call of this host thread, failed: ADCT_OK, or ADCT_E_HIP (the
+ * thread's HIP error state is then cleared).  The one call besides the
+ * batch, server and autotuner calls that synchronises. */
+int adct_check(void* stream);
+
 /* Host copies of the library's constants (Section 2.1): T (row-major,
  * T[u*16+j]), the diagonal s of S = sqrt((T T^T)^-1), and the zonal weights
  * W[u*16+v] = 256 / (d_u d_v), d = diag(T T^T).  Any pointer may be NULL. */

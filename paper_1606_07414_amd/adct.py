@@ -108,6 +108,7 @@ _SIGNATURES = {
     "adct_t8_encode_zonal": (ctypes.c_int, [_PP, ctypes.c_int, _P, _PP, _I32, _P, _P]),
     "adct_t8_encode_quant": (ctypes.c_int, [_PP, ctypes.c_int, _P, _PP, _I32, _P, _P]),
     "adct_mixed_encode": (ctypes.c_int, [_PP, ctypes.c_int, _I64, _P, _P, _PP, _I32, _P, _P]),
+    "adct_check": (ctypes.c_int, [_P]),
     "adct_recon": (ctypes.c_int, [_P, _PP, _P]),
     "adct_sse": (ctypes.c_int, [_PP, _PP, _I32, _P, _P]),
     "adct_fwd2d_quant": (ctypes.c_int, [_PP, ctypes.c_int, _P, _P]),
@@ -461,6 +462,12 @@ def t8_encode_quant(src, qp: int, dst, q=None, image_height=None, sse=None, want
     _check(_lib().adct_t8_encode_quant(ctypes.byref(ps), qp, q.data_ptr() if q is not None else None,
                                        ctypes.byref(pd), ih, sp, _stream(stream)), "t8_encode_quant")
     return sse
+
+
+def check(stream=None):
+    """Waits for `stream` and raises AdctError if its work (or an earlier HIP
+    call of this thread) failed."""
+    _check(_lib().adct_check(_stream(stream)), "check")
 
 
 MIXED_MAX_LAMBDA = 1 << 40

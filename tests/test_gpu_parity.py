@@ -466,3 +466,16 @@ def test_encoder_dequant_rounded_before_rounding_step(codec):
         assert split[0] == 0  # the 16x16 coding is kept for this block
     assert np.array_equal(host(out), want)
     assert s[0] == O.sse(want, plane)
+
+
+def test_check_waits_and_reports_ok():
+    img = synth.ar1_image(4100, 64, 64)
+    x = dev(img)
+    out = torch.empty_like(x)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        sse = adct.encode_zonal(x, 4, out, stream=s)
+    adct.check(s)  # returns once the work on s is done
+    assert s.query()
+    assert sse.cpu().item() == O.sse(O.zonal_reconstruct(img, 4), img)
+    adct.check()
