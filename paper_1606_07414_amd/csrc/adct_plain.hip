@@ -429,10 +429,4 @@ int adct_sse(const adct_plane* a, const adct_plane* b, int32_t image_height, int
     return launched();
 }
 
-int adct_check(void* stream) {
-    const hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
-    const hipError_t last = hipGetLastError();
-    return e == hipSuccess && last == hipSuccess ? ADCT_OK : ADCT_E_HIP;
-}
-
 }  // extern "C"
