@@ -267,7 +267,8 @@ def video(torch, adct, stream, frames=64):
 def uneven_batch(torch, adct, stream, n=4096):
     """4096 uint8 images with sides uniform over the multiples of 16 in
     [64, 2048], coded by one persistent, graph-captured launch (autotuned):
-    coefficients, zonal r = 8 reconstruction and per-image SSE."""
+    coefficients, zonal r = 8 reconstruction and per-image SSE; and the same
+    images quantised at QP 27 (levels, reconstruction, SSE)."""
     import tempfile
     import synth
     sizes = synth.uneven_sizes(n)
@@ -293,6 +294,17 @@ def uneven_batch(torch, adct, stream, n=4096):
            "default_tune_ms": ms_default, "items": b.info()["items"]}
     b.close()
     bd.close()
+    del coefs, b, bd
+    # the same images quantised at QP 27: int16 levels, reconstruction and SSE
+    # (256 + 512 + 256 bytes per tile)
+    levels = [torch.empty((x.numel() // 256, 16, 16), dtype=torch.int16, device="cuda") for x in xs]
+    qtune, _ = adct.autotune(xs, dsts, adct.OP_QUANT, 27, coefs=levels, sses=sses, cache_path=cache, reps=3)
+    bq = adct.Batch(xs, dsts, adct.OP_QUANT, 27, coefs=levels, sses=sses, tune=qtune)
+    msq = timed(torch, lambda: bq.submit(stream), 10, stream)
+    gbq = 1024 * tiles / (msq * 1e-3) / 1e9
+    out["quant_qp27"] = {"tune": qtune.as_dict(), "ms": msq, "tiles_per_s": tiles / (msq * 1e-3), "gbs": gbq,
+                         "frac_of_8tbs": gbq / HBM_PEAK_GBS, "bytes_per_tile": 1024}
+    bq.close()
     return out
 
 
