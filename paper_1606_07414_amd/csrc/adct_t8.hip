@@ -136,6 +136,10 @@ __global__ __launch_bounds__(256) void k_t8(Args8 a) {
     constexpr int kHalf = OP == kQuant8 ? 16 : 32;  // 32-bit words of half a stored block
     __shared__ uint32_t lds[4][64 * (kHalf + 1)];
     __shared__ long long red[2][4];
+    // the block's input rows, kept for the SSE: row i of thread t at
+    // src_rows[i][t] (consecutive threads, consecutive words: no conflicts)
+    constexpr int kRowWords = sizeof(S) == 1 ? 2 : 4;
+    __shared__ uint32_t src_rows[SSE ? 8 : 1][SSE ? 256 * kRowWords : 1];
     // chunk of 256 consecutive blocks taken by this workgroup
     const uint32_t chunk =
         a.spread_rows ? (blockIdx.x % kSpread8) * a.spread_rows + blockIdx.x / kSpread8 : blockIdx.x;
@@ -149,6 +153,20 @@ __global__ __launch_bounds__(256) void k_t8(Args8 a) {
 #pragma unroll
     for (int i = 0; i < 8; ++i)
         raw[i] = load_row8<S>(a.src + (int64_t)(by * 8u + (uint32_t)i) * a.src_pitch + (int64_t)bx * 8 * (int64_t)sizeof(S));
+    if constexpr (SSE) {
+        // the source rows leave L2 long before the SSE needs them again:
+        // keep them in LDS (each thread reads back only its own rows)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            uint32_t* d = &src_rows[i][threadIdx.x * kRowWords];
+            d[0] = raw[i].x;
+            d[1] = raw[i].y;
+            if constexpr (kRowWords == 4) {
+                d[2] = raw[i].z;
+                d[3] = raw[i].w;
+            }
+        }
+    }
     // forward: rows, then columns
     int32_t y[8][8];
 #pragma unroll
@@ -231,10 +249,10 @@ __global__ __launch_bounds__(256) void k_t8(Args8 a) {
         int32_t row[8], x[8];
         inv8(y[i], row);
         if constexpr (SSE) {
-            // read the source row again (it is still in L2) instead of keeping
-            // the block's input live through the whole computation
-            unpack_row8<S>(load_row8<S>(a.src + (int64_t)(by * 8u + (uint32_t)i) * a.src_pitch +
-                                        (int64_t)bx * 8 * (int64_t)sizeof(S)), x);
+            // the source row from LDS rather than live registers through the
+            // whole computation
+            const uint32_t* d = &src_rows[i][threadIdx.x * kRowWords];
+            unpack_row8<S>(kRowWords == 4 ? make_uint4(d[0], d[1], d[2], d[3]) : make_uint4(d[0], d[1], 0u, 0u), x);
         }
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
