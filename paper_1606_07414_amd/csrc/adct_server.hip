@@ -4,15 +4,16 @@
 // admitted, by a publication slot j (slots are handed out in admission order;
 // neither is ever reused within a server).
 //
-// Publication.  The loop takes each request's pixels straight from the
-// caller's pinned host memory: every work item first copies its own sample
-// rows over the host link into the request's pool block, in long contiguous
-// runs, and is then coded from there, so nothing is copied ahead, no other
-// stream is involved, and the transfer of one item overlaps the coding of
-// others.  For each admitted request the host thread writes its 128-byte descriptor into
-// slot j of a ring in host-mapped memory and then stores j + 1 to a
-// host-mapped slot count (release order).  Results (levels and
-// reconstruction) go to the request's block of the device pool.
+// Publication.  For each admitted request the host thread writes its
+// 128-byte descriptor into slot j of a ring in host-mapped memory and then
+// stores j + 1 to a host-mapped slot count (release order).  The loop takes
+// the pixels straight from the caller's pinned host memory: every work item
+// first copies its own sample rows over the host link into the request's
+// pool block, in long contiguous runs, and is then coded from there, so
+// nothing is copied ahead and no other stream is involved.  Items are staged
+// in slot order, at most kStagers at a time, and the coding of one item
+// overlaps the transfer of others.  Results (levels and reconstruction) go
+// to the request's block of the device pool.
 //
 // Loop kernel (persistent).  Workgroup 0 is the dispatcher: one wave polls
 // the host-mapped slot count, copies new descriptors into device memory and
@@ -21,9 +22,9 @@
 // items; for slot j < count it claims item g = atomicAdd(claim[j], 1) and
 // codes it when g < items(j), else marks j exhausted (atomicMax on the low
 // mark) and moves on.  Over-claims are harmless since claim counters are
-// never reused.  Before reading a newly met slot's descriptor and pixels a
-// worker takes a system-scope acquire fence, so that no cache line left over
-// from an earlier user of the same pool memory is read.  After coding an
+// never reused.  Before reading a newly met slot's descriptor a worker
+// takes a system-scope acquire fence, so that no cache line left over from
+// an earlier slot is read.  After coding an
 // item: release fence, then done[j] += 1; the worker that completes slot j
 // posts the SSE and a completion flag (system scope) to the host-mapped
 // record of request k.  The dispatcher ends the loop: on the host's stop
