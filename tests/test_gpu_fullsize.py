@@ -3,9 +3,11 @@
 The batched image workload (1024 uint8 AR(1) images of 512x512) and a batch
 whose images do not hold a multiple of 16 tiles, both large enough that every
 workgroup processes several tile groups and flushes per-image SSE across
-image boundaries; video residual frames at 1920x1088 4:2:0.  Every image's
-SSE is checked against the C oracle; sampled images are compared sample by
-sample with the numpy oracle.
+image boundaries; video residual frames at 1920x1088 4:2:0, one frame at a
+time and as the 64-frame plane stacks that the benchmark codes in one call
+(16-point, 8-point and mixed codecs).  Every image's SSE is checked against
+the C oracle or the squared error of the returned reconstruction; sampled
+images are compared sample by sample with the numpy oracle.
 """
 import numpy as np
 import pytest
@@ -100,3 +102,66 @@ def test_video_residual_frames(qp):
         sse2 = adct.encode_quant(x, qp, out2, q=q2, image_height=hh)
         torch.cuda.synchronize()
         assert torch.equal(q, q2) and torch.equal(out, out2) and torch.equal(sse, sse2)
+
+
+# ---- the video workload as the benchmark launches it -------------------------
+# 64 residual frames of 1920x1088 4:2:0, each plane coded as one stack of 64
+# frames per call: per-frame SSE is spread over many workgroups and split
+# where workgroups cross frames.  Every frame's SSE is checked against the
+# squared error of the returned reconstruction; frames 0, 37 and 63 of every
+# plane are compared with the oracle element by element.
+FRAMES, VIDEO_HEIGHTS, SAMPLED = 64, (1088, 544, 544), (0, 37, 63)
+
+
+@pytest.fixture(scope="module")
+def video_stacks():
+    planes = [[], [], []]
+    for f in range(FRAMES):
+        for i, p in enumerate(synth.video_frame_planes(f)):
+            planes[i].append(p)
+    return [np.concatenate(p) for p in planes]
+
+
+def _frame_sse(out, ref, h):
+    d = out.astype(np.int64) - ref.astype(np.int64)
+    return (d * d).reshape(FRAMES, h, -1).sum(axis=(1, 2))
+
+
+@pytest.mark.parametrize("codec,qp", [("t16", 22), ("t16", 37), ("t8", 27), ("mixed", 27)])
+def test_video_workload_as_benchmarked(video_stacks, codec, qp):
+    from oracle import mixed as X
+    from oracle import t8 as E8
+    lam = int(round(0.57 * 2 ** ((qp - 12) / 3)))
+    for stack, h in zip(video_stacks, VIDEO_HEIGHTS):
+        w = stack.shape[1]
+        x = torch.from_numpy(stack).cuda()
+        out = torch.full_like(x, 77)
+        sse = torch.full((FRAMES,), -1, dtype=torch.int64, device="cuda")
+        if codec == "t8":
+            per = (h // 8) * (w // 8)
+            q = torch.full((x.numel() // 64, 8, 8), -7, dtype=torch.int16, device="cuda")
+            adct.t8_encode_quant(x, qp, out, q=q, image_height=h, sse=sse)
+        else:
+            per = (h // 16) * (w // 16)
+            q = torch.full((x.numel() // 256, 16, 16), -7, dtype=torch.int16, device="cuda")
+            if codec == "t16":
+                adct.encode_quant(x, qp, out, q=q, image_height=h, sse=sse)
+            else:
+                split = torch.full((x.numel() // 256,), 9, dtype=torch.uint8, device="cuda")
+                adct.mixed_encode(x, qp, lam, out, q=q, split=split, image_height=h, sse=sse)
+        torch.cuda.synchronize()
+        got_out, got_q, got_sse = out.cpu().numpy(), q.cpu().numpy(), sse.cpu().numpy()
+        assert np.array_equal(got_sse, _frame_sse(got_out, stack, h)), (codec, qp, h)
+        for f in SAMPLED:
+            res = stack[f * h:(f + 1) * h]
+            fo, fq = got_out[f * h:(f + 1) * h], got_q[f * per:(f + 1) * per]
+            if codec == "t16":
+                wq, _, want = O.quant_reconstruct(res, qp)
+            elif codec == "t8":
+                wq, want = E8.quant_reconstruct8(res, qp)
+            else:
+                ws, wq, want = X.mixed_encode(res, qp, lam)
+                assert np.array_equal(split.cpu().numpy()[f * per:(f + 1) * per], ws), (codec, qp, h, f)
+            assert np.array_equal(fq, wq), (codec, qp, h, f)
+            assert np.array_equal(fo, want), (codec, qp, h, f)
+            assert got_sse[f] == O.sse(want, res), (codec, qp, h, f)
