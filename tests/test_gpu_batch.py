@@ -143,17 +143,28 @@ def test_autotune_and_cache(tmp_path):
         assert torch.equal(dsts[k], out) and torch.equal(coefs[k], c) and torch.equal(sses[k], s)
 
 
-def test_full_size_uneven_batch():
+@pytest.fixture(scope="module")
+def uneven_full():
     # 4096 images, sides uniform over the multiples of 16 in [64, 2048]
     sizes = synth.uneven_sizes(4096)
     pool = synth.crop_pool()
     imgs = [np.ascontiguousarray(synth.crop_from_pool(pool, k, h, w)) for k, (h, w) in enumerate(sizes)]
-    xs = [torch.from_numpy(i).cuda() for i in imgs]
+    return sizes, imgs, [torch.from_numpy(i).cuda() for i in imgs]
+
+
+# the default tuning, and the tunings the autotuner picks on MI355X for the
+# two benchmark legs (zonal r = 8; quantised at QP 27)
+@pytest.mark.parametrize("op,param,tune", [(adct.OP_ZONAL, 8, None), (adct.OP_ZONAL, 8, (32, 1, 4)),
+                                           (adct.OP_QUANT, 27, (32, 2, 8))])
+def test_full_size_uneven_batch(uneven_full, op, param, tune):
+    sizes, imgs, xs = uneven_full
+    zonal = op == adct.OP_ZONAL
     dsts = [torch.empty_like(x) for x in xs]
-    coefs = [torch.empty((x.numel() // 256, 16, 16), dtype=torch.int32, device="cuda") for x in xs]
+    cdt = torch.int32 if zonal else torch.int16
+    coefs = [torch.empty((x.numel() // 256, 16, 16), dtype=cdt, device="cuda") for x in xs]
     sse = torch.empty(4096, dtype=torch.int64, device="cuda")
     sses = [sse[k:k + 1] for k in range(4096)]
-    b = adct.Batch(xs, dsts, adct.OP_ZONAL, 8, coefs=coefs, sses=sses)
+    b = adct.Batch(xs, dsts, op, param, coefs=coefs, sses=sses, tune=adct.make_tune(*tune) if tune else None)
     b.submit()
     b.submit()
     torch.cuda.synchronize()
@@ -162,11 +173,17 @@ def test_full_size_uneven_batch():
     rng = np.random.default_rng(0)
     for k in sorted(set(rng.integers(0, 4096, size=48).tolist()) | {0, 4095}):
         img = imgs[k]
-        c_coef = oracle_c.fwd2d_u8(img)
-        c_out, c_sse = oracle_c.zonal_recon_u8(c_coef, img.shape[0], img.shape[1], 8, img, img.shape[0])
-        assert got[k] == c_sse[0], k
-        assert np.array_equal(dsts[k].cpu().numpy(), c_out), k
-        assert np.array_equal(coefs[k].cpu().numpy(), c_coef.astype(np.int32)), k
+        if zonal:
+            c_coef = oracle_c.fwd2d_u8(img)
+            want_out, c_sse = oracle_c.zonal_recon_u8(c_coef, img.shape[0], img.shape[1], 8, img, img.shape[0])
+            want_sse, want_c = c_sse[0], c_coef.astype(np.int32)
+        else:
+            want_c, _, want_out = O.quant_reconstruct(img, param, 0, 255)
+            want_sse = O.sse(want_out, img)
+        assert got[k] == want_sse, k
+        assert np.array_equal(dsts[k].cpu().numpy(), want_out), k
+        assert np.array_equal(coefs[k].cpu().numpy(), want_c), k
     # every image's SSE equals the single-image encoder's
     for k in range(0, 4096, 7):
-        assert int(got[k]) == int(_single(xs[k], adct.OP_ZONAL, 8)[2].item()), k
+        assert int(got[k]) == int(_single(xs[k], op, param)[2].item()), k
+    b.close()
