@@ -220,3 +220,34 @@ def test_pitched_pinned_request_and_plain_pageable():
     plain.wait_all(30)
     _check_all(plain, [t], [img])
     plain.close()
+
+
+@pytest.mark.parametrize("mode", [adct.SERVE_PERSISTENT, adct.SERVE_PLAIN])
+def test_benchmark_configuration_full_size_requests(mode):
+    # the serving benchmark's server and request mix: sides log-uniform in
+    # [256, 4096] with the largest and smallest sides forced in, requests of
+    # equal side sharing one pinned crop, Poisson arrivals at 2000 req/s, a
+    # 16 GiB pool, 512 in flight, work items sized per request and two loop
+    # workgroups per CU; results are held (not auto-released) to be checked
+    n = 48
+    sides = [int(s) for s in synth.request_sides(n - 2, seed=24_000)] + [4096, 256]
+    rng = np.random.default_rng(24_001)
+    pool = [synth.ar1_image(24_100 + i, 4096, 4096) for i in range(2)]
+    bufs = {}
+    for s in sorted(set(sides)):
+        p, y, x = int(rng.integers(0, 2)), int(rng.integers(0, 4096 - s + 1)), int(rng.integers(0, 4096 - s + 1))
+        bufs[s] = torch.from_numpy(np.ascontiguousarray(pool[p][y:y + s, x:x + s])).pin_memory()
+    views = [bufs[s] for s in sides]
+    arr = synth.poisson_arrivals(2000.0, n, seed=24_002)
+    srv = adct.Server(pool_bytes=16 << 30, qp=QP, mode=mode, max_inflight=512, max_requests=n, tiles_per_item=0,
+                      wgs_per_cu=2)
+    t0 = adct.now_ns() + 5_000_000
+    tickets = [srv.submit(v, t0 + int(a * 1e9)) for v, a in zip(views, arr)]
+    srv.wait_all(120)
+    st = srv.stats()
+    assert st["completed"] == n and st["cancelled"] == 0
+    assert st["tiles_completed"] == sum(s * s // 256 for s in sides)
+    # every result against the same image coded alone; requests 0, 23 and
+    # 46 (the 4096 x 4096 one) against the oracle as well
+    _check_all(srv, tickets, [v.numpy() for v in views], oracle_every=23)
+    srv.close()
