@@ -1,6 +1,8 @@
 """GPU parity for Section 3.1's experiment as the paper runs it: zig-zag
 retention of the first r coefficients (bit-exact against the oracle) and the
-SSIM index (float64 on both sides, within 1e-9 relative)."""
+SSIM index (float64 on both sides, within 1e-9 relative); and, at the
+experiment's full size (1024 images of 512x512 in one call), the zig-zag
+encoder and the comparison codecs."""
 import numpy as np
 import pytest
 
@@ -154,3 +156,48 @@ def test_ssim_full_size_batch_sampled():
         want = E.ssim(img[k * 512:(k + 1) * 512], o[k * 512:(k + 1) * 512])
         assert got[k] == pytest.approx(want, rel=SSIM_RTOL), k
     assert np.all((got > 0.3) & (got < 1.0))
+
+
+@pytest.fixture(scope="module")
+def full_batch():
+    img = synth.ar1_batch(1024, 512, 512)
+    return img, dev(img)
+
+
+@pytest.mark.parametrize("codec,kind,r", [("zigzag", None, 21), ("zigzag", None, 150), ("wht", "zigzag", 21),
+                                          ("wht", "zonal", 4), ("dct", "zonal", 4), ("dct", "zigzag", 105)])
+def test_image_experiment_codecs_full_size(full_batch, codec, kind, r):
+    # the launch shape of the image-experiment benchmark (1024 images of
+    # 512x512, one call): every image's SSE against the squared error of the
+    # returned reconstruction; images 0, 517 and 1023 against the oracle
+    from oracle import comparison as CMP
+    img, x = full_batch
+    out = torch.full_like(x, 5)
+    sse = torch.full((1024,), -1, dtype=torch.int64, device="cuda")
+    coef = None
+    if codec == "zigzag":
+        coef = torch.full((x.numel() // 256, 16, 16), -3, dtype=torch.int32, device="cuda")
+        adct.encode_zigzag(x, r, out, coef=coef, image_height=512, sse=sse)
+    else:
+        xf = adct.XF_WHT if codec == "wht" else adct.XF_DCT
+        keep = adct.KEEP_ZIGZAG if kind == "zigzag" else adct.KEEP_ZONAL
+        adct.compare_encode(x, xf, keep, r, out, image_height=512, sse=sse)
+    got, s = host(out).astype(np.int64), host(sse)
+    d = got - img.astype(np.int64)
+    assert np.array_equal(s, (d * d).reshape(1024, -1).sum(axis=1))
+    ckind = CMP.ZIGZAG if kind == "zigzag" else CMP.ZONAL
+    for k in (0, 517, 1023):
+        sl = slice(k * 512, (k + 1) * 512)
+        if codec == "zigzag":
+            assert np.array_equal(got[sl], E.zigzag_reconstruct(img[sl], r)), k
+            assert np.array_equal(host(coef[k * 1024:(k + 1) * 1024]), O.fwd2d(img[sl])), k
+        elif codec == "wht":
+            assert np.array_equal(got[sl], CMP.wht_reconstruct(img[sl], ckind, r)), k
+        else:
+            # fp32 on the matrix cores against float64: equal away from
+            # rounding ties, within one step at them
+            real = CMP.dct_reconstruct_real(img[sl], ckind, r)
+            want = CMP.dct_reconstruct(img[sl], ckind, r).astype(np.int64)
+            near = np.abs(real - np.floor(real) - 0.5) < 1e-3
+            assert np.array_equal(got[sl][~near], want[~near]), k
+            assert np.all(np.abs(got[sl] - want) <= 1), k
