@@ -61,7 +61,9 @@ constexpr int lds_words(int tpw) { return tpw * kIntTile; }
 
 enum InKind { kInSamples = 0, kInY = 1, kInZfix = 2, kInQ = 3 };
 enum CStore { kStoreNone = 0, kStoreY = 1, kStoreQ = 2 };
-enum Mid { kMidNone = 0, kMidZonal = 1, kMidQuant = 2, kMidDequant = 3, kMidZigzag = 4 };
+// kMidQuantFit quantises like kMidQuant for inputs whose levels are known
+// to fit int16, without the saturation.
+enum Mid { kMidNone = 0, kMidZonal = 1, kMidQuant = 2, kMidDequant = 3, kMidZigzag = 4, kMidQuantFit = 5 };
 enum OutKind { kOutNothing = 0, kOutSamples = 1, kOutBlocks = 2 };
 
 // XF selects the transform: kXfProposed (T) or kXfWht (comparison).
@@ -132,16 +134,19 @@ __device__ __forceinline__ void load_rows(const PlaneRef& pl, uint32_t by, uint3
     }
 }
 
-// Exact SSE of the two output rows r0, r1 (values in the sample range)
-// against packed input pairs: 16-bit differences, squared and accumulated
-// two at a time by v_dot2_i32_i16.
+// Exact SSE of the two output rows r0, r1 (clamped 8-fraction-bit values,
+// whose samples are byte 1 (uint8) or bytes 1-2 (int16)) against packed
+// input pairs: 16-bit differences, squared and accumulated two at a time by
+// v_dot2_i32_i16.
+template <typename S>
 __device__ __forceinline__ int32_t pair_sse(const int32_t (&r0)[16], const int32_t (&r1)[16],
                                             const uint32_t (&xk)[16]) {
     typedef short s16x2 __attribute__((ext_vector_type(2)));
     int32_t s = 0;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
-        const uint32_t o = perm((uint32_t)r1[j], (uint32_t)r0[j], 0x05040100u);
+        const uint32_t o = sizeof(S) == 1 ? perm((uint32_t)r1[j], (uint32_t)r0[j], 0x0c050c01u)
+                                          : perm((uint32_t)r1[j], (uint32_t)r0[j], 0x06050201u);
         const s16x2 d = __builtin_bit_cast(s16x2, o) - __builtin_bit_cast(s16x2, xk[j]);
         s = __builtin_amdgcn_sdot2(d, d, s, false);
     }
@@ -351,6 +356,9 @@ __device__ __forceinline__ void zigzag_weights_cols(int p, int r, int32_t (&a)[1
     }
 }
 
+// Levels of columns p, p+8, saturated to int16 when SAT (without SAT the
+// caller guarantees that they fit).
+template <bool SAT>
 __device__ __forceinline__ void quant_cols(const Scale5& qs, int p, const int32_t (&a)[16], const int32_t (&b)[16],
                                            int32_t (&qa)[16], int32_t (&qb)[16]) {
     float fa[3], fb[3];
@@ -358,8 +366,12 @@ __device__ __forceinline__ void quant_cols(const Scale5& qs, int p, const int32_
     column_factors(qs, p + 8, fb);
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
-        qa[u] = clamp_i32(round_away(__fmul_rn((float)a[u], fa[log2_norm(u) - 2])), -32768, 32767);
-        qb[u] = clamp_i32(round_away(__fmul_rn((float)b[u], fb[log2_norm(u) - 2])), -32768, 32767);
+        qa[u] = round_away(__fmul_rn((float)a[u], fa[log2_norm(u) - 2]));
+        qb[u] = round_away(__fmul_rn((float)b[u], fb[log2_norm(u) - 2]));
+        if constexpr (SAT) {
+            qa[u] = clamp_i32(qa[u], -32768, 32767);
+            qb[u] = clamp_i32(qb[u], -32768, 32767);
+        }
     }
 }
 
@@ -375,18 +387,45 @@ __device__ __forceinline__ void dequant_cols(const Scale5& dqs, int p, int32_t (
 }
 
 // ---- inverse ---------------------------------------------------------------
-// Rounded, clamped sample: floor(R / 256) within [lo, hi] (R already holds
-// the +128).  Clamping before the shift keeps the compiler from forming
-// v_ashr_pk_u8_i32, whose upper result bits are not cleared before they are
-// OR-ed with the other bytes of a packed row.
+// Rounded, clamped sample kept in 8-fraction-bit fixed point: R (already
+// holding the +128) clamped to [lo * 256, hi * 256 + 255].  The sample
+// floor(R / 256) is then byte 1 of the result (uint8, in [0, 255]) or bytes
+// 1-2 (int16, in [-255, 255] as a two's-complement halfword), so byte
+// permutes pick it out with no shift.
 template <typename S>
-__device__ __forceinline__ int32_t out_sample(int32_t R) {
-    return clamp_i32(R, Samples<S>::kLo * 256, Samples<S>::kHi * 256 + 255) >> 8;
+__device__ __forceinline__ int32_t out_fixed(int32_t R) {
+    return clamp_i32(R, Samples<S>::kLo * 256, Samples<S>::kHi * 256 + 255);
 }
 
+// The samples of two out_fixed values as 16-bit lanes (a low, b high):
+// uint8 zero-extended, int16 as is, the layout of pack_rows.
 template <typename S>
-__device__ __forceinline__ void store_row(char* p, const int32_t (&o)[16]) {
-    Samples<S>::store(p, o);
+__device__ __forceinline__ uint32_t pack_fixed_pair(int32_t a, int32_t b) {
+    if constexpr (sizeof(S) == 1)
+        return perm((uint32_t)b, (uint32_t)a, 0x0c050c01u);
+    else
+        return perm((uint32_t)b, (uint32_t)a, 0x06050201u);
+}
+
+// Stores the 16 samples of a row of out_fixed values.
+template <typename S>
+__device__ __forceinline__ void store_row_fixed(char* p, const int32_t (&o)[16]) {
+    if constexpr (sizeof(S) == 1) {
+        uint32_t ws[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t lo = perm((uint32_t)o[4 * k + 1], (uint32_t)o[4 * k], 0x0c0c0501u);
+            const uint32_t hi = perm((uint32_t)o[4 * k + 3], (uint32_t)o[4 * k + 2], 0x05010c0cu);
+            ws[k] = lo | hi;
+        }
+        store16(p, make_uint4(ws[0], ws[1], ws[2], ws[3]));
+    } else {
+        uint32_t ws[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) ws[k] = pack_fixed_pair<S>(o[2 * k], o[2 * k + 1]);
+        store16(p, make_uint4(ws[0], ws[1], ws[2], ws[3]));
+        store16(p + 16, make_uint4(ws[4], ws[5], ws[6], ws[7]));
+    }
 }
 
 // ---- per-image SSE accumulated across the groups of a workgroup ------------
@@ -497,9 +536,12 @@ __device__ __forceinline__ void process_group(const GroupArgs& a, uint32_t g0, u
             lds_blocks_to_global<TPW>(lds, tid, ntile, static_cast<int32_t*>(a.cout) + (int64_t)g0 * 256);
         }
     }
-    if constexpr (M::MID == kMidQuant) {
+    if constexpr (M::MID == kMidQuant || M::MID == kMidQuantFit) {
+        // uint8 samples give |Y s_u s_v| <= 16 * 255 = 4080 and 1 / Delta <
+        // 1.6, so their levels always fit int16
+        constexpr bool sat = M::MID == kMidQuant && sizeof(S) == 2;
         int32_t qa[16], qb[16];
-        quant_cols(qs, cp, ya, yb, qa, qb);
+        quant_cols<sat>(qs, cp, ya, yb, qa, qb);
         if constexpr (M::STORE == kStoreQ) {
             if (a.cout) {
                 __syncthreads();
@@ -560,18 +602,18 @@ __device__ __forceinline__ void process_group(const GroupArgs& a, uint32_t g0, u
     } else {
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
-            r0[j] = out_sample<S>(r0[j]);
-            r1[j] = out_sample<S>(r1[j]);
+            r0[j] = out_fixed<S>(r0[j]);
+            r1[j] = out_fixed<S>(r1[j]);
         }
         if (rok) {
             char* pa = const_cast<char*>(row_ptr<S>(a.dst, rby, rbx, rip));
-            store_row<S>(pa, r0);
-            store_row<S>(pa + 8 * a.dst.pitch, r1);
+            store_row_fixed<S>(pa, r0);
+            store_row_fixed<S>(pa + 8 * a.dst.pitch, r1);
         }
         if constexpr (M::SSE) {
           if (a.sse) {
             if constexpr (M::IN != kInSamples) pack_rows<S>(ra0, ra1, rb0, rb1, xk);
-            int32_t s = rok ? pair_sse(r0, r1, xk) : 0;
+            int32_t s = rok ? pair_sse<S>(r0, r1, xk) : 0;
             // a group inside one image adds to the workgroup's running sum
             // (flushed when the image changes); a group that straddles
             // images adds per thread

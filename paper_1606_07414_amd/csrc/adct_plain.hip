@@ -76,6 +76,27 @@ int launch_typed(int32_t dtype, uint32_t nblk, hipStream_t s, const GroupArgs& a
     return dtype == ADCT_U8 ? launch_group<uint8_t, M>(nblk, s, a) : launch_group<int16_t, M>(nblk, s, a);
 }
 
+// Whether every level of an int16 plane (samples within [-2047, 2047]) fits
+// int16 with these quantiser factors.  In class c (d_u d_v = 2^(c+4)) every
+// coefficient has |Y| <= d_u d_v * 2047, T's entries being 0 or +-1; a bound
+// below 32767 keeps the fp32 product below 32767.5, so its level is at most
+// 32767 in magnitude.  (It holds from QP 4 on; uint8 planes always fit.)
+bool i16_levels_fit(const Scale5Host& qs) {
+    for (int c = 0; c < 5; ++c)
+        if ((double)qs.f[c] * 2047.0 * (double)(16 << c) >= 32767.0) return false;
+    return true;
+}
+
+// Quantising modes: int16 planes whose levels provably fit skip the
+// saturation (kMidQuantFit); uint8 planes never need it, and their kMidQuant
+// kernels leave it out.
+template <int STORE, int OUT, bool SSE>
+int launch_quant(int32_t dtype, bool fit, uint32_t nblk, hipStream_t s, const GroupArgs& a) {
+    if (dtype == ADCT_U8) return launch_group<uint8_t, Mode<kInSamples, STORE, kMidQuant, OUT, -1, SSE>>(nblk, s, a);
+    if (fit) return launch_group<int16_t, Mode<kInSamples, STORE, kMidQuantFit, OUT, -1, SSE>>(nblk, s, a);
+    return launch_group<int16_t, Mode<kInSamples, STORE, kMidQuant, OUT, -1, SSE>>(nblk, s, a);
+}
+
 // Zonal modes: uint8 planes get kernels specialised for the common sizes,
 // in which the known-zero coefficients fold away.
 template <int IN, int STORE, bool SSE>
@@ -141,8 +162,8 @@ int adct_fwd2d_quant(const adct_plane* src, int qp, int16_t* q, void* stream) {
     set_geometry(src, a);
     a.cout = q;
     a.qs = to_dev(qs);
-    return launch_typed<Mode<kInSamples, kStoreQ, kMidQuant, kOutNothing, -1, false>>(
-        src->dtype, (uint32_t)nblk, static_cast<hipStream_t>(stream), a);
+    return launch_quant<kStoreQ, kOutNothing, false>(src->dtype, i16_levels_fit(qs), (uint32_t)nblk,
+                                                     static_cast<hipStream_t>(stream), a);
 }
 
 int adct_inv2d(const int32_t* coef, int64_t nblk, int32_t* out, void* stream) {
@@ -396,11 +417,13 @@ int adct_encode_quant(const adct_plane* src, int qp, int16_t* q, const adct_plan
     a.dqs = to_dev(dqs);
     if ((rc = prepare_sse(dst, src, image_height, sse, s, a))) return rc;
     const uint32_t n = (uint32_t)nblk;
+    const int32_t dt = src->dtype;
+    const bool fit = i16_levels_fit(qs);
     if (q)
-        return sse ? launch_typed<Mode<kInSamples, kStoreQ, kMidQuant, kOutSamples, -1, true>>(src->dtype, n, s, a)
-                   : launch_typed<Mode<kInSamples, kStoreQ, kMidQuant, kOutSamples, -1, false>>(src->dtype, n, s, a);
-    return sse ? launch_typed<Mode<kInSamples, kStoreNone, kMidQuant, kOutSamples, -1, true>>(src->dtype, n, s, a)
-               : launch_typed<Mode<kInSamples, kStoreNone, kMidQuant, kOutSamples, -1, false>>(src->dtype, n, s, a);
+        return sse ? launch_quant<kStoreQ, kOutSamples, true>(dt, fit, n, s, a)
+                   : launch_quant<kStoreQ, kOutSamples, false>(dt, fit, n, s, a);
+    return sse ? launch_quant<kStoreNone, kOutSamples, true>(dt, fit, n, s, a)
+               : launch_quant<kStoreNone, kOutSamples, false>(dt, fit, n, s, a);
 }
 
 int adct_sse(const adct_plane* a, const adct_plane* b, int32_t image_height, int64_t* sse, void* stream) {

@@ -345,6 +345,31 @@ def test_encode_quant(qp, store, kind):
         assert s[i] == O.sse(want[i * 64:(i + 1) * 64], src[i * 64:(i + 1) * 64])
 
 
+@pytest.mark.parametrize("qp", [0, 3, 4, 5])
+def test_encode_quant_i16_extreme_levels(qp):
+    # constant +-2047 tiles give the largest level, DC = 256 * 2047 / (16
+    # Delta) = 32752 / Delta: saturated to int16 below QP 4 (Delta < 1),
+    # exact from QP 4 on, where the library leaves the saturation out
+    i = np.arange(16)
+    chk = np.where((i[:, None] + i[None, :]) % 2 == 0, 2047, -2047)
+    blocks = [np.full((16, 16), 2047), np.full((16, 16), -2047), chk, synth.laplacian_residual(qp, 16, 16)]
+    src = np.concatenate(blocks, axis=1).astype(np.int16)
+    x = dev(src)
+    out = torch.empty_like(x)
+    q = torch.zeros((4, 16, 16), dtype=torch.int16, device="cuda")
+    s = host(adct.encode_quant(x, qp, out, q=q, image_height=16))
+    qw = np.clip(O.quantise(O.fwd2d(src), qp), -32768, 32767)
+    want = O.from_tiles(O.round_clamp(O.reconstruct_fixed(O.dequantise(qw, qp)), -255, 255), *src.shape)
+    assert np.array_equal(host(q), qw)
+    assert np.array_equal(host(out), want)
+    assert s[0] == O.sse(want, src)
+    assert np.array_equal(host(adct.fwd2d_quant(x, qp)), qw)
+    if qp < 4:
+        assert qw[0, 0, 0] == 32767 and qw[1, 0, 0] == -32768
+    else:
+        assert qw[0, 0, 0] == O.quantise(O.fwd2d(src), qp)[0, 0, 0] < 32767
+
+
 def test_encoders_match_two_pass_paths():
     img = synth.ar1_batch(3, 128, 192, seed_base=900)
     x = dev(img)
