@@ -58,6 +58,24 @@ def test_quant_tables_match_oracle_bit_exact(qp):
     assert np.array_equal(dqs.view(np.uint32), odqs.view(np.uint32))
 
 
+def test_int16_levels_fit_from_qp4_on():
+    # The fused quantising encoders saturate levels to int16 only where a
+    # level can leave int16.  |Y[u][v]| <= d_u d_v max|x| since T's entries
+    # are 0 and +-1, so with int16 samples within [-2047, 2047] the largest
+    # level magnitude is max over (u, v) of d_u d_v 2047 qs[u][v] (rounded):
+    # below 32767 from QP 4 on, above it below QP 4.  Checked on the
+    # library's own fp32 tables; uint8 samples never come close.
+    T, _, _ = adct.constants()
+    d = (T.astype(np.int64) ** 2).sum(axis=1)
+    for qp in range(64):
+        qs, _ = adct.quant_tables(qp)
+        top = float((np.outer(d, d) * qs.astype(np.float64)).max())
+        assert (top * 2047 < 32767) == (qp >= 4), qp
+        assert top * 255 < 8000, qp
+    # the bound is reached: an all-2047 tile has DC = 256 * 2047
+    assert float(adct.quant_tables(4)[0][0, 0]) * 256 * 2047 == pytest.approx(32752, rel=1e-6)
+
+
 def test_quant_tables_reject_bad_qp():
     with pytest.raises(adct.AdctError):
         adct.quant_tables(64)
