@@ -51,6 +51,16 @@ bool quant_scales(int qp, Scale5Host* qs, Scale5Host* dqs) {
     return true;
 }
 
+// In class c (d_u d_v = 2^(c+4)) every coefficient has |Y| <= d_u d_v * 2047,
+// T's entries being 0 or +-1; a bound below 32767 keeps the fp32 product
+// below 32767.5, so its level is at most 32767 in magnitude.  (uint8 planes,
+// |Y s_u s_v| <= 4080, always fit.)
+bool i16_levels_fit(const Scale5Host& qs) {
+    for (int c = 0; c < 5; ++c)
+        if ((double)qs.f[c] * 2047.0 * (double)(16 << c) >= 32767.0) return false;
+    return true;
+}
+
 void ortho_scales(Scale5Host* ss) {
     for (int c = 0; c < 5; ++c) ss->f[c] = (float)class_ss(c);
 }

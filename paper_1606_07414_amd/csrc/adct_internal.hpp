@@ -15,6 +15,10 @@ struct Scale5Host {
 
 // Quantiser / dequantiser factors per class for `qp` (false if out of range).
 bool quant_scales(int qp, Scale5Host* qs, Scale5Host* dqs);
+// Whether every quantisation level of an int16 plane (samples within
+// [-2047, 2047]) fits int16 with the 16-point quantiser factors `qs`, so that
+// the saturation to int16 can be left out (true from QP 4 on).
+bool i16_levels_fit(const Scale5Host& qs);
 // fp32(s_u s_v) per class.
 void ortho_scales(Scale5Host* ss);
 // class c = log2 d_u + log2 d_v - 4 of coefficient (u, v).

@@ -144,7 +144,10 @@ typedef short s16x2 __attribute__((ext_vector_type(2)));
 // column i's levels, row i's reconstruction and its shares of D and R.  fq /
 // fd are the lane's quantiser / dequantiser factors for column i, indexed by
 // row_class(u).
-template <typename S, bool EIGHT>
+// SAT: saturate the levels to int16.  Only the 16-point coding of int16
+// samples below QP 4 can need it; the 8-point levels stay within
+// 8 * 2047 / Delta < 26000 (sqrt(d_u d_v) <= 8 for T8).
+template <typename S, bool EIGHT, bool SAT>
 __device__ __forceinline__ void code(const int32_t (&x)[16], const uint32_t (&xw)[8], int32_t* t, int i,
                                      const float (&fq)[3], const float (&fd)[3], Coded& c) {
     constexpr int kBits = EIGHT ? 6 : 8;
@@ -158,9 +161,12 @@ __device__ __forceinline__ void code(const int32_t (&x)[16], const uint32_t (&xw
     c.r = 0;
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
-        const int32_t q = clamp_i32(round_away(__fmul_rn((float)b[u], fq[row_class<EIGHT>(u)])), -32768, 32767);
+        const float v = __fmul_rn((float)b[u], fq[row_class<EIGHT>(u)]);
+        const float h = copysignf(0x1.fffffep-2f, v);
+        int32_t q = round_away_h(v, h);
+        if constexpr (SAT) q = clamp_i32(q, -32768, 32767);
         c.r += q != 0;
-        b[u] = round_away(__fmul_rn((float)q, fd[row_class<EIGHT>(u)]));
+        b[u] = round_away_h(__fmul_rn((float)q, fd[row_class<EIGHT>(u)]), h);
         if (u & 1)
             c.q[u >> 1] |= (uint32_t)q << 16;
         else
@@ -208,8 +214,8 @@ __device__ __forceinline__ int32_t region_sum(int32_t v) {
     return v;
 }
 
-template <typename S, bool SSE>
-__global__ __launch_bounds__(256) void k_mixed(MixArgs a) {
+template <typename S, bool SSE, bool SAT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_mixed(MixArgs a) {
     __shared__ int32_t lds[4][4 * kRegion];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, i = lane & 15;
@@ -244,8 +250,8 @@ __global__ __launch_bounds__(256) void k_mixed(MixArgs a) {
 #pragma unroll
         for (int m = 0; m < 8; ++m) xw[m] = __builtin_amdgcn_perm((uint32_t)x[2 * m + 1], (uint32_t)x[2 * m], 0x05040100u);
         Coded c16, c8;
-        code<S, false>(x, xw, t, i, fq16, fd16, c16);
-        code<S, true>(x, xw, t, i, fq8, fd8, c8);
+        code<S, false, SAT>(x, xw, t, i, fq16, fd16, c16);
+        code<S, true, false>(x, xw, t, i, fq8, fd8, c8);
         const int32_t d16 = region_sum(c16.d), d8 = region_sum(c8.d);
         const int32_t rr = region_sum(c16.r | (c8.r << 16));
         const long long j16 = (long long)d16 + a.lambda * (long long)(rr & 0xffff);
@@ -362,16 +368,22 @@ int adct_mixed_encode(const adct_plane* src, int qp, int64_t lambda, int16_t* q,
     a.per_wave = 4 * ((steps + waves - 1) / waves);
     const uint32_t nwaves = (a.nreg + a.per_wave - 1) / a.per_wave;
     const dim3 grid((nwaves + 3) / 4);
+    // uint8 levels always fit int16; int16 ones unless QP < 4
     if (src->dtype == ADCT_U8) {
         if (sse)
-            hipLaunchKernelGGL((k_mixed<uint8_t, true>), grid, dim3(256), 0, s, a);
+            hipLaunchKernelGGL((k_mixed<uint8_t, true, false>), grid, dim3(256), 0, s, a);
         else
-            hipLaunchKernelGGL((k_mixed<uint8_t, false>), grid, dim3(256), 0, s, a);
+            hipLaunchKernelGGL((k_mixed<uint8_t, false, false>), grid, dim3(256), 0, s, a);
+    } else if (i16_levels_fit(qs)) {
+        if (sse)
+            hipLaunchKernelGGL((k_mixed<int16_t, true, false>), grid, dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_mixed<int16_t, false, false>), grid, dim3(256), 0, s, a);
     } else {
         if (sse)
-            hipLaunchKernelGGL((k_mixed<int16_t, true>), grid, dim3(256), 0, s, a);
+            hipLaunchKernelGGL((k_mixed<int16_t, true, true>), grid, dim3(256), 0, s, a);
         else
-            hipLaunchKernelGGL((k_mixed<int16_t, false>), grid, dim3(256), 0, s, a);
+            hipLaunchKernelGGL((k_mixed<int16_t, false, true>), grid, dim3(256), 0, s, a);
     }
     return launched();
 }

@@ -76,17 +76,6 @@ int launch_typed(int32_t dtype, uint32_t nblk, hipStream_t s, const GroupArgs& a
     return dtype == ADCT_U8 ? launch_group<uint8_t, M>(nblk, s, a) : launch_group<int16_t, M>(nblk, s, a);
 }
 
-// Whether every level of an int16 plane (samples within [-2047, 2047]) fits
-// int16 with these quantiser factors.  In class c (d_u d_v = 2^(c+4)) every
-// coefficient has |Y| <= d_u d_v * 2047, T's entries being 0 or +-1; a bound
-// below 32767 keeps the fp32 product below 32767.5, so its level is at most
-// 32767 in magnitude.  (It holds from QP 4 on; uint8 planes always fit.)
-bool i16_levels_fit(const Scale5Host& qs) {
-    for (int c = 0; c < 5; ++c)
-        if ((double)qs.f[c] * 2047.0 * (double)(16 << c) >= 32767.0) return false;
-    return true;
-}
-
 // Quantising modes: int16 planes whose levels provably fit skip the
 // saturation (kMidQuantFit); uint8 planes never need it, and their kMidQuant
 // kernels leave it out.

@@ -31,4 +31,13 @@ __host__ __device__ __forceinline__ int32_t round_away(float x) {
 #endif
 }
 
+// round_away(y) given h = copysign(0x1.fffffep-2f, x) for an x of y's sign,
+// or any x when y is zero: a dequantised level y = level * dqs has the sign
+// of the quantised value x it came from, so the quantiser's addend serves
+// both roundings.
+__device__ __forceinline__ int32_t round_away_h(float y, float h) {
+#pragma clang fp contract(off)
+    return (int32_t)(y + h);
+}
+
 }  // namespace adct

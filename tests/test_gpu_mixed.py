@@ -47,7 +47,7 @@ def check(src, qp, lam, image_height=None):
     return ws
 
 
-@pytest.mark.parametrize("qp", [4, 22, 27, 32, 37, 51])
+@pytest.mark.parametrize("qp", [0, 3, 4, 22, 27, 32, 37, 51])
 @pytest.mark.parametrize("lam", [0, 6, 58, 1 << 40])
 def test_mixed_i16_residuals(qp, lam):
     # 7 regions per block row: a wave's four regions straddle block rows
@@ -101,6 +101,45 @@ def test_mixed_optional_outputs_and_pitch():
     q = torch.zeros((24, 16, 16), dtype=torch.int16, device="cuda")
     adct.mixed_encode(wide[:, 32:128], 32, 40, out[:, 32:128], q=q, want_sse=False)
     assert np.array_equal(host(q), wq)
+
+
+@pytest.mark.parametrize("qp", [0, 3, 4, 27])
+def test_mixed_regions_equal_the_standalone_codecs(qp):
+    # each region's levels and reconstruction are those of the codec it
+    # chose, coded alone by adct_encode_quant (16x16) or adct_t8_encode_quant
+    # (8x8), level saturation included: constant +-2047 regions give 16x16
+    # DC levels of 32752 / Delta, saturated to int16 below QP 4
+    i = np.arange(16)
+    chk = np.where((i[:, None] + i[None, :]) % 2 == 0, 2047, -2047)
+    quad = np.kron(np.array([[2047, -2047], [-1000, 600]]), np.ones((8, 8), np.int64))
+    top = np.concatenate([np.full((16, 16), 2047), np.full((16, 16), -2047), chk, quad,
+                          synth.laplacian_residual(3600 + qp, 16, 16)], axis=1)
+    src = np.concatenate([top, synth.laplacian_residual(3700 + qp, 16, 80)]).astype(np.int16)
+    x = dev(src)
+    o16, o8 = torch.empty_like(x), torch.empty_like(x)
+    q16 = torch.empty((10, 16, 16), dtype=torch.int16, device="cuda")
+    q8 = torch.empty((40, 8, 8), dtype=torch.int16, device="cuda")
+    adct.encode_quant(x, qp, o16, q=q16, want_sse=False)
+    adct.t8_encode_quant(x, qp, o8, q=q8, want_sse=False)
+    h16, h8, p16, p8 = host(q16), host(q8), host(o16), host(o8)
+    if qp < 4:
+        assert h16[0, 0, 0] == 32767 and h16[1, 0, 0] == -32768
+    for lam in (0, 18, 1 << 40):
+        split, q, out, s = run(src, qp, lam, image_height=32)
+        for k in range(10):
+            by, bx = divmod(k, 5)
+            rows, cols = slice(16 * by, 16 * by + 16), slice(16 * bx, 16 * bx + 16)
+            if split[k]:
+                for a in range(2):
+                    for b in range(2):
+                        blk = h8[(2 * by + a) * 10 + 2 * bx + b]
+                        assert np.array_equal(q[k, 8 * a:8 * a + 8, 8 * b:8 * b + 8], blk), (lam, k, a, b)
+                assert np.array_equal(out[rows, cols], p8[rows, cols]), (lam, k)
+            else:
+                assert np.array_equal(q[k], h16[k]), (lam, k)
+                assert np.array_equal(out[rows, cols], p16[rows, cols]), (lam, k)
+        d = out.astype(np.int64) - src
+        assert s[0] == (d * d).sum()
 
 
 def test_mixed_sse_over_many_waves_and_images():
