@@ -76,6 +76,17 @@ def test_int16_levels_fit_from_qp4_on():
     assert float(adct.quant_tables(4)[0][0, 0]) * 256 * 2047 == pytest.approx(32752, rel=1e-6)
 
 
+def test_t8_levels_never_leave_int16():
+    # The 8-point quantising codecs store levels without saturation: with
+    # |Y8[u][v]| <= d_u d_v 2047 (int16 samples within [-2047, 2047]) the
+    # largest level is below 26000 at every QP, on the library's own tables.
+    T8 = adct.t8_constants()[0]
+    d = (T8.astype(np.int64) ** 2).sum(axis=1)
+    for qp in range(64):
+        qs8, _ = adct.t8_quant_tables(qp)
+        assert float((np.outer(d, d) * qs8.astype(np.float64)).max()) * 2047 < 26000, qp
+
+
 def test_quant_tables_reject_bad_qp():
     with pytest.raises(adct.AdctError):
         adct.quant_tables(64)
