@@ -453,7 +453,9 @@ def main():
     ms_step = 1000.0 * wall / args.steps
     tiles_per_step = ntiles * len(RS)
     # average duration of one call (the encoder and its SSE clear)
-    enc_avg_ms = float(np.mean([a.elapsed_time(b) for a, b in ev])) / len(RS)
+    step_ms = [a.elapsed_time(b) for a, b in ev]
+    enc_avg_ms = float(np.mean(step_ms)) / len(RS)
+    enc_median_ms = float(np.median(step_ms)) / len(RS)
     # per r, for context, after the timed region
     enc_ms = {}
     for r in RS:
@@ -516,6 +518,7 @@ def main():
                      "achieved": enc_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": enc_gbs / HBM_PEAK_GBS,
                      "traffic": traffic, "bytes_per_tile": ENC_BYTES_PER_TILE, "tiles_per_launch": ntiles,
                      "algorithmic_bytes_per_launch": ENC_BYTES_PER_TILE * ntiles, "avg_launch_ms": enc_avg_ms,
+                     "median_launch_ms": enc_median_ms,
                      "copy_probe_gbs": probe["gbs"],
                      "distinct_inputs": {"avg_launch_ms": distinct_ms, "achieved": distinct_gbs,
                                          "frac": distinct_gbs / HBM_PEAK_GBS,
