@@ -389,15 +389,6 @@ def quant_reconstruct(plane: np.ndarray, qp: int, lo: int = -255, hi: int = 255)
     return q, z, out
 
 
-def quant_reconstruct_real(plane: np.ndarray, qp: int) -> np.ndarray:
-    """Real-valued codec: C-hat^T (round(B / Delta) Delta) C-hat in float64."""
-    H, W = plane.shape
-    q, _ = quantise_fp64(fwd2d(plane), qp)
-    C = orthogonal_approximation()
-    Bh = dequantise_fp64(q, qp)
-    return from_tiles(np.einsum("ui,kuv,vj->kij", C, Bh, C, optimize=True), H, W)
-
-
 # --------------------------------------------------------------------------
 # Quality measures (Section 3.1 PSNR; Section 3.2 per-plane PSNR).
 # --------------------------------------------------------------------------
