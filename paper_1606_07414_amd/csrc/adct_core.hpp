@@ -673,7 +673,10 @@ constexpr uint32_t kSseSpreadMin = ADCT_SSE_SPREAD_MIN;
 // chunk b; otherwise the grid is kSseSpread x spread_rows and workgroup b
 // takes chunk (b % kSseSpread) * spread_rows + b / kSseSpread (workgroups
 // past the last chunk exit at once).
-template <int TPW, typename S, typename M>
+// PF = false is the form for gpw == 1: with no next group to prefetch, no
+// registers are held for one while the group is coded, which keeps the SSE
+// modes at 5 waves per SIMD instead of 4.
+template <int TPW, typename S, typename M, bool PF>
 __global__ __launch_bounds__(TPW * 8) void k_group(GroupArgs a, uint32_t nblk, uint32_t gpw, uint32_t spread_rows) {
     __shared__ uint32_t lds[lds_words(TPW)];
     __shared__ long long red[TPW * 8 / 64];
@@ -683,13 +686,18 @@ __global__ __launch_bounds__(TPW * 8) void k_group(GroupArgs a, uint32_t nblk, u
         spread_rows ? (blockIdx.x % kSseSpread) * spread_rows + blockIdx.x / kSseSpread : blockIdx.x;
     uint32_t g0 = chunk * gpw * (uint32_t)TPW;
     if (g0 >= nblk) return;
-    const uint32_t gend = min(nblk, g0 + gpw * (uint32_t)TPW);
     if constexpr (M::IN == kInSamples) load_group_rows<TPW, S>(a, g0, min((uint32_t)TPW, nblk - g0), rows);
-    for (uint32_t k = 0; g0 < gend; ++k, g0 += (uint32_t)TPW) {
-        if (k) __syncthreads();  // the previous group's LDS reads are done
-        const uint32_t g0n = g0 + (uint32_t)TPW;
-        const uint32_t ntn = g0n < gend ? min((uint32_t)TPW, gend - g0n) : 0u;
-        process_group<TPW, S, M>(a, g0, min((uint32_t)TPW, nblk - g0), lds, red, acc, rows, a, g0n, ntn, a.qs,
+    if constexpr (PF) {
+        const uint32_t gend = min(nblk, g0 + gpw * (uint32_t)TPW);
+        for (uint32_t k = 0; g0 < gend; ++k, g0 += (uint32_t)TPW) {
+            if (k) __syncthreads();  // the previous group's LDS reads are done
+            const uint32_t g0n = g0 + (uint32_t)TPW;
+            const uint32_t ntn = g0n < gend ? min((uint32_t)TPW, gend - g0n) : 0u;
+            process_group<TPW, S, M>(a, g0, min((uint32_t)TPW, nblk - g0), lds, red, acc, rows, a, g0n, ntn, a.qs,
+                                     a.dqs);
+        }
+    } else {
+        process_group<TPW, S, M>(a, g0, min((uint32_t)TPW, nblk - g0), lds, red, acc, rows, a, 0u, 0u, a.qs,
                                  a.dqs);
     }
     if constexpr (M::SSE) {

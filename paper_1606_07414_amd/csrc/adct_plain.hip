@@ -67,7 +67,10 @@ int launch_group(uint32_t nblk, hipStream_t s, const GroupArgs& a) {
     const bool spread = M::SSE && a.sse && a.image_tiles / span > kSseSpreadMin;
     const uint32_t rows = spread ? (chunks + kSseSpread - 1) / kSseSpread : 0u;
     const uint32_t grid = rows ? rows * kSseSpread : chunks;
-    hipLaunchKernelGGL((k_group<kTPW, S, M>), dim3(grid), dim3(kTPW * 8), 0, s, a, nblk, gpw, rows);
+    if (gpw == 1)
+        hipLaunchKernelGGL((k_group<kTPW, S, M, false>), dim3(grid), dim3(kTPW * 8), 0, s, a, nblk, gpw, rows);
+    else
+        hipLaunchKernelGGL((k_group<kTPW, S, M, true>), dim3(grid), dim3(kTPW * 8), 0, s, a, nblk, gpw, rows);
     return launched();
 }
 
