@@ -29,6 +29,8 @@
  * - Coefficient-domain arrays are block-major: [nblk][16][16], block
  *   k = by * (width/16) + bx in raster order, element u*16 + v, u the
  *   vertical and v the horizontal frequency.  They must be 16-byte aligned.
+ *   A call on nblk == 0 blocks launches nothing and returns ADCT_OK once its
+ *   other arguments are valid; its array pointers may then be NULL.
  * - A batch of equally sized images is passed as one tall plane (images
  *   stacked vertically); `image_height` then names each image's height so
  *   that per-image sums of squared errors can be formed.

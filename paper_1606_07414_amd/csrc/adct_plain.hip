@@ -38,7 +38,9 @@ int launched() { return hipGetLastError() == hipSuccess ? ADCT_OK : ADCT_E_HIP; 
 unsigned elem_grid(uint64_t n4) { return (unsigned)std::min<uint64_t>((n4 + 255) / 256, 1u << 20); }
 
 int check_blocks(const void* p, int64_t nblk) {
-    if (!p || nblk < 0 || nblk > (int64_t)INT32_MAX) return ADCT_E_ARG;
+    if (nblk < 0 || nblk > (int64_t)INT32_MAX) return ADCT_E_ARG;
+    if (nblk == 0) return ADCT_OK;  // an empty array may be a null pointer
+    if (!p) return ADCT_E_ARG;
     if (!aligned16(p)) return ADCT_E_ALIGN;
     return ADCT_OK;
 }

@@ -458,9 +458,10 @@ int adct_t8_fwd2d(const adct_plane* src, int32_t* coef, void* stream) {
 }
 
 int adct_t8_inv2d(const int32_t* coef, int64_t nblk, int32_t* out, void* stream) {
-    if (!coef || !out || nblk < 0 || nblk > (int64_t)INT32_MAX - 256) return ADCT_E_ARG;
+    if (nblk < 0 || nblk > (int64_t)INT32_MAX - 256) return ADCT_E_ARG;
+    if (nblk == 0) return ADCT_OK;  // an empty array may be a null pointer
+    if (!coef || !out) return ADCT_E_ARG;
     if ((((uintptr_t)coef) & 15) || (((uintptr_t)out) & 15)) return ADCT_E_ALIGN;
-    if (nblk == 0) return ADCT_OK;
     hipLaunchKernelGGL(k_t8_inv, dim3((unsigned)((nblk + 255) / 256)), dim3(256), 0, static_cast<hipStream_t>(stream),
                        coef, out, (uint32_t)nblk);
     return launched();

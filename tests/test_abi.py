@@ -169,6 +169,20 @@ def test_empty_block_arrays_are_noops():
     assert lib.adct_quant(FAKE, 0, 27, FAKE, None) == adct.OK
     assert lib.adct_dequant(FAKE, 0, 27, FAKE, None) == adct.OK
     assert lib.adct_zonal(FAKE, 0, 4, FAKE, None) == adct.OK
+    # an empty array may be a null pointer (what an empty device tensor gives)
+    assert lib.adct_inv2d(None, 0, None, None) == adct.OK
+    assert lib.adct_scale(None, 0, None, None) == adct.OK
+    assert lib.adct_quant(None, 0, 27, None, None) == adct.OK
+    assert lib.adct_dequant(None, 0, 27, None, None) == adct.OK
+    assert lib.adct_zonal(None, 0, 4, None, None) == adct.OK
+    assert lib.adct_zigzag(None, 0, 150, None, None) == adct.OK
+    assert lib.adct_t8_inv2d(None, 0, None, None) == adct.OK
+    # the other arguments are still checked, and a null pointer with blocks is not accepted
+    assert lib.adct_quant(None, 0, 64, None, None) == adct.E_ARG
+    assert lib.adct_zonal(None, 0, 17, None, None) == adct.E_ARG
+    assert lib.adct_inv2d(None, 1, FAKE, None) == adct.E_ARG
+    assert lib.adct_inv2d(FAKE, 1, None, None) == adct.E_ARG
+    assert lib.adct_t8_inv2d(None, 1, FAKE, None) == adct.E_ARG
 
 
 def test_recon_reference_rules():

@@ -104,6 +104,31 @@ def test_inv2d(nblk):
     assert np.array_equal(host(adct.inv2d(dev(Y))), O.inv2d(Y))
 
 
+def test_empty_block_arrays_through_binding():
+    """Zero blocks: empty device tensors (null data pointers) give empty
+    results and launch nothing; the other arguments are still checked."""
+    e32 = torch.empty((0, 16, 16), dtype=torch.int32, device="cuda")
+    e16 = torch.empty((0, 16, 16), dtype=torch.int16, device="cuda")
+    assert adct.inv2d(e32).shape == (0, 16, 16)
+    assert adct.scale(e32).shape == (0, 16, 16)
+    assert adct.quant(e32, 27).shape == (0, 16, 16)
+    assert adct.dequant(e16, 27).shape == (0, 16, 16)
+    assert adct.zonal(e32, 4).shape == (0, 16, 16)
+    assert adct.zigzag(e32, 150).shape == (0, 16, 16)
+    assert adct.t8_inv2d(torch.empty((0, 8, 8), dtype=torch.int32, device="cuda")).shape == (0, 8, 8)
+    with pytest.raises(adct.AdctError):
+        adct.quant(e32, 64)
+    with pytest.raises(adct.AdctError):
+        adct.zonal(e32, 17)
+    # a plane with no rows is not a plane of 16 x 16 blocks
+    with pytest.raises(adct.AdctError):
+        adct.fwd2d(torch.empty((0, 16), dtype=torch.uint8, device="cuda"))
+    adct.check()
+    # the stream still works after the empty calls
+    x = synth.ar1_image(5, 32, 48)
+    assert np.array_equal(host(adct.fwd2d(dev(x))), O.fwd2d(x))
+
+
 def test_inverse_then_forward_identity_on_gpu_output():
     # T (T^T Y T) T^T = D Y D, with the GPU computing T^T Y T
     T = O.transform_matrix()
