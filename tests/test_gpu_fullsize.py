@@ -165,3 +165,90 @@ def test_video_workload_as_benchmarked(video_stacks, codec, qp):
             assert np.array_equal(fq, wq), (codec, qp, h, f)
             assert np.array_equal(fo, want), (codec, qp, h, f)
             assert got_sse[f] == O.sse(want, res), (codec, qp, h, f)
+
+
+# ---------------------------------------------------------------- maximum sizes
+# A 4 GiB uint8 plane (1 049 600 x 4096, 16 793 600 tiles) coded in one call:
+# byte offsets of the plane pass 2^31 and 2^32, those of the int32
+# coefficients 2^31, 2^32 and 2^34, those of the int16 levels 2^31 and 2^32.
+# The oracle checks tiles sampled on each side of every such boundary (read
+# back from the device input); the per-image SSE is checked against the
+# squared error of the returned reconstruction over the whole plane.
+BIG_H, BIG_W = 1_049_600, 4096
+BIG_TPR = BIG_W // 16
+
+
+def _big_plane():
+    x = torch.empty((BIG_H, BIG_W), dtype=torch.uint8, device="cuda")
+    j = torch.arange(BIG_W, dtype=torch.int64, device="cuda")[None, :]
+    for r0 in range(0, BIG_H, 16384):
+        i = torch.arange(r0, min(BIG_H, r0 + 16384), dtype=torch.int64, device="cuda")[:, None]
+        v = ((i * 2654435761) ^ (j * 2246822519) ^ ((i >> 4) * (j >> 4) * 97)) & 0xFFFFFFFF
+        x[r0:r0 + i.shape[0]] = (v >> 24).to(torch.uint8)
+    return x
+
+
+def _sample_tiles():
+    nt = BIG_H // 16 * BIG_TPR
+    marks = [0, nt - 1]
+    for b in (2 ** 31 // 1024, 2 ** 32 // 1024, 2 ** 34 // 1024,      # int32 coefficients
+              2 ** 31 // 512, 2 ** 32 // 512,                          # int16 levels
+              (2 ** 31 // BIG_W) // 16 * BIG_TPR, (2 ** 32 // BIG_W) // 16 * BIG_TPR):  # plane rows
+        marks += [b - BIG_TPR - 1, b - 1, b, b + 1, b + BIG_TPR]
+    rng = np.random.default_rng(1234)
+    marks += rng.integers(0, nt, size=48).tolist()
+    return np.array(sorted({m for m in marks if 0 <= m < nt}), dtype=np.int64)
+
+
+def _tiles(plane, t):
+    by = torch.from_numpy(t // BIG_TPR).cuda()
+    bx = torch.from_numpy(t % BIG_TPR).cuda()
+    return plane.view(BIG_H // 16, 16, BIG_TPR, 16)[by, :, bx, :].cpu().numpy()
+
+
+def _sse_of(out, x, image_h):
+    sse = []
+    for i0 in range(0, BIG_H, image_h):
+        s = torch.zeros((), dtype=torch.int64, device="cuda")
+        for r0 in range(i0, i0 + image_h, 16384):
+            r1 = min(i0 + image_h, r0 + 16384)
+            d = out[r0:r1].to(torch.int32) - x[r0:r1].to(torch.int32)
+            s += (d * d).sum(dtype=torch.int64)
+        sse.append(int(s.item()))
+    return np.array(sse, dtype=np.int64)
+
+
+def test_plane_beyond_4gib_zonal_and_quant():
+    image_h = BIG_H // 4
+    x = _big_plane()
+    nt = BIG_H // 16 * BIG_TPR
+    t = _sample_tiles()
+    xt = _tiles(x, t)
+    print(f"[big plane] {BIG_H}x{BIG_W}, {nt} tiles, {len(t)} sampled", flush=True)
+    # zonal r = 8 with int32 coefficients (groups of several tiles per workgroup)
+    coef = torch.empty((nt, 16, 16), dtype=torch.int32, device="cuda")
+    out = torch.empty_like(x)
+    sse = adct.encode_zonal(x, 8, out, coef=coef, image_height=image_h)
+    adct.check()
+    got_coef = coef[torch.from_numpy(t).cuda()].cpu().numpy()
+    got_out = _tiles(out, t)
+    for k in range(len(t)):
+        assert np.array_equal(got_coef[k], O.fwd2d(xt[k])[0]), f"coefficients of tile {t[k]}"
+        assert np.array_equal(got_out[k], O.zonal_reconstruct(xt[k], 8)), f"reconstruction of tile {t[k]}"
+    assert np.array_equal(sse.cpu().numpy(), _sse_of(out, x, image_h))
+    del coef
+    torch.cuda.empty_cache()
+    # quantised at QP 27 with int16 levels
+    q = torch.empty((nt, 16, 16), dtype=torch.int16, device="cuda")
+    sse_q = adct.encode_quant(x, 27, out, q=q, image_height=image_h)
+    adct.check()
+    got_q = q[torch.from_numpy(t).cuda()].cpu().numpy()
+    got_out = _tiles(out, t)
+    for k in range(len(t)):
+        want_q = O.quantise(O.fwd2d(xt[k]), 27)
+        assert np.array_equal(got_q[k], want_q[0]), f"levels of tile {t[k]}"
+        rec = O.from_tiles(O.round_clamp(O.reconstruct_fixed(O.dequantise(want_q, 27)), 0, 255), 16, 16)
+        assert np.array_equal(got_out[k], rec), f"quantised reconstruction of tile {t[k]}"
+    assert np.array_equal(sse_q.cpu().numpy(), _sse_of(out, x, image_h))
+    del x, out, q
+    torch.cuda.empty_cache()
