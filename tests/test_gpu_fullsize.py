@@ -13,6 +13,8 @@ import numpy as np
 import pytest
 
 from oracle import adct_oracle as O
+from oracle import mixed as MX
+from oracle import t8 as E8
 import synth
 from tests import oracle_c
 
@@ -251,4 +253,58 @@ def test_plane_beyond_4gib_zonal_and_quant():
         assert np.array_equal(got_out[k], rec), f"quantised reconstruction of tile {t[k]}"
     assert np.array_equal(sse_q.cpu().numpy(), _sse_of(out, x, image_h))
     del x, out, q
+    torch.cuda.empty_cache()
+
+
+def _sample_blocks8():
+    bpr = BIG_W // 8
+    nb = BIG_H // 8 * bpr
+    marks = [0, nb - 1]
+    for b in (2 ** 31 // 128, 2 ** 32 // 128,                               # int16 levels of 8x8 blocks
+              (2 ** 31 // BIG_W) // 8 * bpr, (2 ** 32 // BIG_W) // 8 * bpr):  # plane rows
+        marks += [b - bpr - 1, b - 1, b, b + 1, b + bpr]
+    rng = np.random.default_rng(4321)
+    marks += rng.integers(0, nb, size=48).tolist()
+    return np.array(sorted({m for m in marks if 0 <= m < nb}), dtype=np.int64)
+
+
+def test_plane_beyond_4gib_t8_and_mixed():
+    """The same 4 GiB plane through the 8-point quantising encoder (67 M
+    blocks of 8x8) and the mixed 8/16-point codec (16.8 M regions)."""
+    image_h = BIG_H // 4
+    x = _big_plane()
+    nt = BIG_H // 16 * BIG_TPR
+    out = torch.empty_like(x)
+    q = torch.empty((nt * 256,), dtype=torch.int16, device="cuda")
+    # T8 at QP 27
+    b8 = _sample_blocks8()
+    print(f"[big plane] T8: {nt * 4} blocks, {len(b8)} sampled", flush=True)
+    sse8 = adct.t8_encode_quant(x, 27, out, q=q.view(nt * 4, 8, 8), image_height=image_h)
+    adct.check()
+    idx = torch.from_numpy(b8).cuda()
+    bpr = BIG_W // 8
+    xb = x.view(BIG_H // 8, 8, bpr, 8)[idx // bpr, :, idx % bpr, :].cpu().numpy()
+    ob = out.view(BIG_H // 8, 8, bpr, 8)[idx // bpr, :, idx % bpr, :].cpu().numpy()
+    qb = q.view(nt * 4, 8, 8)[idx].cpu().numpy()
+    for k in range(len(b8)):
+        want_q, want_o = E8.quant_reconstruct8(xb[k], 27, 0, 255)
+        assert np.array_equal(qb[k], want_q[0]), f"T8 levels of block {b8[k]}"
+        assert np.array_equal(ob[k], want_o), f"T8 reconstruction of block {b8[k]}"
+    assert np.array_equal(sse8.cpu().numpy(), _sse_of(out, x, image_h))
+    # mixed 8/16-point coding at QP 27, lambda 18
+    t = _sample_tiles()
+    print(f"[big plane] mixed: {nt} regions, {len(t)} sampled", flush=True)
+    split = torch.empty(nt, dtype=torch.uint8, device="cuda")
+    ssem = adct.mixed_encode(x, 27, 18, out, q=q.view(nt, 16, 16), split=split, image_height=image_h)
+    adct.check()
+    ti = torch.from_numpy(t).cuda()
+    xt, ot = _tiles(x, t), _tiles(out, t)
+    qt, st = q.view(nt, 16, 16)[ti].cpu().numpy(), split[ti].cpu().numpy()
+    for k in range(len(t)):
+        w_split, w_levels, w_out = MX.mixed_encode(xt[k], 27, 18, 0, 255)
+        assert st[k] == w_split[0], f"mixed decision of region {t[k]}"
+        assert np.array_equal(qt[k], w_levels[0]), f"mixed levels of region {t[k]}"
+        assert np.array_equal(ot[k], w_out), f"mixed reconstruction of region {t[k]}"
+    assert np.array_equal(ssem.cpu().numpy(), _sse_of(out, x, image_h))
+    del x, out, q, split
     torch.cuda.empty_cache()
