@@ -82,8 +82,12 @@ __global__ __launch_bounds__(TPW * 8) void k_batch(BatchArgs b, const GroupArgs*
         SseAcc acc{0, kNoImage};
         bool have_next = false;
         ItemDev nitem = item;
-        for (uint32_t g0 = item.first, k = 0; g0 < gend; g0 += (uint32_t)TPW, ++k) {
-            if (k) __syncthreads();  // the previous group's LDS reads are done
+        for (uint32_t g0 = item.first; g0 < gend; g0 += (uint32_t)TPW) {
+            // the previous group's LDS reads are done, also across items: the
+            // last group of the previous item ends in LDS reads (its inverse
+            // row pass) and the SSE flush between items, which would
+            // otherwise order them, is skipped for jobs without an SSE output
+            __syncthreads();
             uint32_t g0n = g0 + (uint32_t)TPW;
             uint32_t ntn = g0n < gend ? min((uint32_t)TPW, gend - g0n) : 0u;
             if (g0n >= gend) {

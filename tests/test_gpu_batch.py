@@ -125,6 +125,30 @@ def test_optional_outputs():
         assert torch.equal(dsts[k], _single(x, adct.OP_ZONAL, 8)[0])
 
 
+# Items of several groups with neither coefficients nor SSE requested: the
+# first group of an item must not overwrite LDS that the last group of the
+# previous item is still reading (no SSE flush orders them then).
+@pytest.mark.parametrize("op,param", [(adct.OP_ZONAL, 8), (adct.OP_QUANT, 27)])
+@pytest.mark.parametrize("tpg,gpi,wpc", [(16, 2, 2), (8, 3, 4), (32, 2, 8), (16, 64, 1), (8, 64, 16)])
+def test_multi_group_items_without_optional_outputs(op, param, tpg, gpi, wpc):
+    imgs, xs = _images(41, 64, 768, seed=14_500)
+    dsts = [torch.full_like(x, 7) for x in xs]
+    b = adct.Batch(xs, dsts, op, param, tune=adct.make_tune(tpg, gpi, wpc))
+    for _ in range(2):
+        b.submit()
+    torch.cuda.synchronize()
+    for k, x in enumerate(xs):
+        assert torch.equal(dsts[k], _single(x, op, param)[0]), k
+    for k in (0, 20, 40):
+        img = imgs[k]
+        if op == adct.OP_ZONAL:
+            want = O.zonal_reconstruct(img, param)
+        else:
+            want = O.quant_reconstruct(img, param, 0, 255)[2]
+        assert np.array_equal(dsts[k].cpu().numpy(), want), k
+    b.close()
+
+
 def test_autotune_and_cache(tmp_path):
     imgs, xs = _images(64, 64, 512, seed=15_000)
     dsts, coefs, sses = _outputs(xs, adct.OP_ZONAL)
