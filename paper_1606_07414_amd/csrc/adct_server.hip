@@ -226,7 +226,9 @@ __global__ __launch_bounds__(kServeTPW * 8) void k_serve(ServeArgs s) {
         __syncthreads();  // the previous item is finished with LDS and sh_*
         if (tid == 0) {
             uint32_t j = max(sh_cursor, load_sys(s.low));
-            const uint32_t cnt = load_sys(s.count);
+            // acquire: the descriptors of slots below the count, which the
+            // dispatcher stored before advancing it, are read after it
+            const uint32_t cnt = __hip_atomic_load(s.count, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
             uint32_t res_j = 0xffffffffu, res_g = 0;
             while (j < cnt) {
                 const uint32_t n = load_sys(&s.desc[j].nitems);
@@ -269,6 +271,9 @@ __global__ __launch_bounds__(kServeTPW * 8) void k_serve(ServeArgs s) {
         }
         const uint32_t* dw = reinterpret_cast<const uint32_t*>(sh_desc);
         const uint32_t nitems = rfl(dw[8]), tpi = rfl(dw[9]), nblk = rfl(dw[17]), req = rfl(dw[18]);
+        // the claim was checked against the item count read during the scan;
+        // the descriptor read after the acquire is the one that counts
+        if (g >= nitems) continue;
         const uint32_t t0 = g * tpi;
         const uint32_t gend = min(nblk, t0 + tpi);
         // The host link serves requests in order: an item is staged once
@@ -714,6 +719,7 @@ int adct_server_create(adct_server** out, const adct_server_cfg* cfg_in) {
     if (ok && cfg.mode == ADCT_SERVE_PERSISTENT) {
         const size_t state_words = 192 + 3 * n;
         ok = hipMalloc(reinterpret_cast<void**>(&S->d_desc), n * sizeof(ReqDesc)) == hipSuccess &&
+             hipMemset(S->d_desc, 0, n * sizeof(ReqDesc)) == hipSuccess &&
              hipMalloc(reinterpret_cast<void**>(&S->d_state), state_words * sizeof(uint32_t)) == hipSuccess &&
              hipMemset(S->d_state, 0, state_words * sizeof(uint32_t)) == hipSuccess &&
              hipHostMalloc(reinterpret_cast<void**>(&S->h_desc), n * sizeof(ReqDesc), mapped) == hipSuccess &&
