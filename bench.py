@@ -69,6 +69,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-other", action="store_true", help="only the batched-image workload")
     ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--detail", default=os.path.join(ROOT, "gpurun_out", "bench_detail.json"),
+                    help="JSON file for the full results (the stdout line holds a summary)")
     return ap.parse_args()
 
 
@@ -408,6 +410,43 @@ def cpu_baseline(img: np.ndarray):
     return out
 
 
+def summary_line(full: dict) -> dict:
+    """The one line printed on stdout: the headline, its roofline and CPU
+    baseline, and one or two figures per other workload.  Everything else
+    stays in the detail file."""
+    keep = ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better", "scaling",
+            "vs_baseline", "dtype", "data", "config", "roofline", "codec_form", "cpu_baseline", "detail_file")
+    line = {k: full[k] for k in keep if k in full}
+    if "cpu_baseline" in line:
+        cb = line["cpu_baseline"]
+        line["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample") if k in cb}
+    other = full.get("other_workloads")
+    if other:
+        summ = {}
+        v = other.get("video_residuals_64x1920x1088")
+        if v:
+            summ["video_fused_ms_per_qp"] = {str(q): round(r["fused_ms"], 4) for q, r in v["qp"].items()}
+            summ["video_fused_frac"] = {str(q): round(r["fused_gbs"] / HBM_PEAK_GBS, 3) for q, r in v["qp"].items()}
+        b = other.get("uneven_batch_4096")
+        if b:
+            summ["uneven_batch"] = {"tiles": b["tiles"], "zonal_r8_ms": round(b["ms"], 3),
+                                    "zonal_r8_frac": round(b["frac_of_8tbs"], 3),
+                                    "quant_qp27_ms": round(b["quant_qp27"]["ms"], 3),
+                                    "quant_qp27_frac": round(b["quant_qp27"]["frac_of_8tbs"], 3)}
+        sv = other.get("serving_poisson")
+        if sv:
+            summ["serving_p50_p99_ms"] = {
+                str(lam): {m: [round(row[m]["p50_ms"], 3), round(row[m]["p99_ms"], 3)] for m in row}
+                for lam, row in sv["rate"].items()}
+            if "capacity" in sv:
+                summ["serving_capacity_tiles_per_s"] = {m: c["tiles_per_s"] for m, c in sv["capacity"].items()}
+        zz = other.get("image_experiment_zigzag_1024x512x512")
+        if zz:
+            summ["zigzag_psnr_db"] = {str(r): round(v["psnr_db"], 2) for r, v in zz["r"].items() if r in (10, 45, 150)}
+        line["other_workloads"] = summ
+    return line
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -425,6 +464,10 @@ def main():
 
     dev = torch.device("cuda:0")
     x = torch.from_numpy(img).to(dev)
+    # one copy of the images per call of a step: a call never finds the
+    # images it reads in the 256 MB Infinity Cache (the previous call read
+    # another copy), so the step streams every byte from HBM
+    copies = [x] + [x.clone() for _ in range(len(RS) - 1)]
     coef = torch.empty((ntiles, 16, 16), dtype=torch.int32, device=dev)
     out = torch.empty_like(x)
     sse = {r: torch.empty(n_img, dtype=torch.int64, device=dev) for r in RS}
@@ -436,8 +479,8 @@ def main():
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
 
     def step():
-        for r in RS:
-            adct.encode_zonal(x, r, out, coef=coef, image_height=SIDE, sse=sse[r], stream=stream)
+        for xc, r in zip(copies, RS):
+            adct.encode_zonal(xc, r, out, coef=coef, image_height=SIDE, sse=sse[r], stream=stream)
 
     for _ in range(args.warmup):
         step()
@@ -449,56 +492,61 @@ def main():
         ev[k][1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
+    print(f"[bench] timed region: {args.steps} steps in {wall:.3f} s", file=sys.stderr, flush=True)
 
     ms_step = 1000.0 * wall / args.steps
     tiles_per_step = ntiles * len(RS)
-    # average duration of one call (the encoder and its SSE clear)
+    # average duration of one call, from the events of the timed region
     step_ms = [a.elapsed_time(b) for a, b in ev]
     enc_avg_ms = float(np.mean(step_ms)) / len(RS)
     enc_median_ms = float(np.median(step_ms)) / len(RS)
-    # per r, for context, after the timed region
-    enc_ms = {}
-    for r in RS:
-        enc_ms[r] = timed(torch, lambda: adct.encode_zonal(x, r, out, coef=coef, image_height=SIDE, sse=sse[r],
-                                                            stream=stream), 10, stream)
     enc_gbs = ENC_BYTES_PER_TILE * ntiles / (enc_avg_ms * 1e-3) / 1e9
     psnr = {r: float(np.mean(adct.psnr(sse[r].cpu().numpy(), SIDE * SIDE))) for r in RS}
-    # context, after the measured region: the same five calls, each on its
-    # own copy of the images.  In a step every call reads the images the
-    # previous call read, and the 256 MB Infinity Cache still holds part of
-    # them; with distinct copies no call can reuse that, so this rate is the
-    # encoder's streaming rate from HBM alone
-    copies = [x] + [x.clone() for _ in range(len(RS) - 1)]
 
-    def step_distinct():
-        for xc, r in zip(copies, RS):
-            adct.encode_zonal(xc, r, out, coef=coef, image_height=SIDE, sse=sse[r], stream=stream)
-    distinct_ms = timed(torch, step_distinct, 5, stream) / len(RS)
-    distinct_gbs = ENC_BYTES_PER_TILE * ntiles / (distinct_ms * 1e-3) / 1e9
-    del copies, step_distinct
-    torch.cuda.empty_cache()
+    # context, after the measured region: the five calls of a step on the
+    # same images, as a codec re-coding one image set would issue them; a
+    # part of the images is then served by the Infinity Cache
+    def step_same():
+        for r in RS:
+            adct.encode_zonal(x, r, out, coef=coef, image_height=SIDE, sse=sse[r], stream=stream)
+    same_ms = timed(torch, step_same, 5, stream) / len(RS)
+    same_gbs = ENC_BYTES_PER_TILE * ntiles / (same_ms * 1e-3) / 1e9
+    # per r, each call on the next copy of the images
+    enc_ms = {}
+    for i, r in enumerate(RS):
+        ring = [0]
 
-    # context, after the measured region: the same coding with two kernels
-    # (coefficients written to HBM and read back)
-    two = {}
-    for r in RS:
-        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
-        adct.fwd2d(x, coef, stream=stream)
-        adct.zonal_recon(coef, r, out, ref=x, image_height=SIDE, sse=sse[r], stream=stream)
-        e0.record(stream)
-        for _ in range(5):
-            adct.fwd2d(x, coef, stream=stream)
-        e1.record(stream)
-        for _ in range(5):
-            adct.zonal_recon(coef, r, out, ref=x, image_height=SIDE, sse=sse[r], stream=stream)
-        e2.record(stream)
-        e2.synchronize()
-        two[r] = (e0.elapsed_time(e1) / 5, e1.elapsed_time(e2) / 5)
-    fwd_ms = float(np.mean([v[0] for v in two.values()]))
+        def one(r=r):
+            adct.encode_zonal(copies[ring[0] % len(copies)], r, out, coef=coef, image_height=SIDE, sse=sse[r],
+                              stream=stream)
+            ring[0] += 1
+        enc_ms[r] = timed(torch, one, 10, stream)
+
+    # the codec form: the forward transform writes the int32 coefficients to
+    # HBM, a second kernel reads back the kept r x r of them, inverts and
+    # writes the reconstruction and SSE (each call on its own image copy)
+    e = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+          torch.cuda.Event(enable_timing=True)) for _ in range(3 * len(RS))]
+    adct.fwd2d(copies[0], coef, stream=stream)
+    k = 0
+    for rep in range(3):
+        for i, r in enumerate(RS):
+            e[k][0].record(stream)
+            adct.fwd2d(copies[i], coef, stream=stream)
+            e[k][1].record(stream)
+            adct.zonal_recon(coef, r, out, ref=copies[i], image_height=SIDE, sse=sse[r], stream=stream)
+            e[k][2].record(stream)
+            k += 1
+    torch.cuda.synchronize()
+    fwd_ms = float(np.mean([a.elapsed_time(b) for a, b, _ in e]))
+    rec_ms = {r: float(np.mean([e[rep * len(RS) + i][1].elapsed_time(e[rep * len(RS) + i][2]) for rep in range(3)]))
+              for i, r in enumerate(RS)}
+    codec_ms = fwd_ms + float(np.mean(list(rec_ms.values())))
+    moved = FWD_BYTES_PER_TILE + float(np.mean([recon_bytes_per_tile(r) for r in RS]))
     probe = copy_probe(torch, stream)
     traffic = encoder_traffic()
 
-    result = {
+    full = {
         "metric": "16x16 blocks/s (fwd+inv) and fraction of HBM peak",
         "value": tiles_per_step / (ms_step * 1e-3),
         "unit": "16x16 blocks/s",
@@ -512,26 +560,31 @@ def main():
         "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": f"{n_img} uint8 AR(1) rho=0.95 images of {SIDE}x{SIDE} ({ntiles} tiles); "
-                               f"per step, for each r in {list(RS)}: fwd2d + zonal r x r + inverse + per-image SSE",
+                               f"per step, for each r in {list(RS)}: fwd2d + zonal r x r + inverse + per-image "
+                               f"SSE, each r on its own copy of the images",
                    "images": n_img, "side": SIDE, "zonal_r": list(RS)},
-        "roofline": {"bound": "hbm", "kernel": "encode_zonal (k_group fwd + coef + zonal inverse + SSE)",
+        "roofline": {"bound": "hbm", "kernel": "encode_zonal (fwd + int32 coefficients + zonal inverse + SSE)",
                      "achieved": enc_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": enc_gbs / HBM_PEAK_GBS,
                      "traffic": traffic, "bytes_per_tile": ENC_BYTES_PER_TILE, "tiles_per_launch": ntiles,
-                     "algorithmic_bytes_per_launch": ENC_BYTES_PER_TILE * ntiles, "avg_launch_ms": enc_avg_ms,
-                     "median_launch_ms": enc_median_ms,
-                     "copy_probe_gbs": probe["gbs"],
-                     "distinct_inputs": {"avg_launch_ms": distinct_ms, "achieved": distinct_gbs,
-                                         "frac": distinct_gbs / HBM_PEAK_GBS,
-                                         "note": "each call of a step on its own copy of the images: "
-                                                 "no reuse of the re-read images through the Infinity Cache"}},
+                     "avg_launch_ms": enc_avg_ms, "median_launch_ms": enc_median_ms,
+                     "traffic_note": "L2-to-fabric bytes (FETCH_SIZE x2, WRITE_SIZE x1, scales from the 1 GiB "
+                                     "copy); Infinity Cache hits count as fetched",
+                     "frac_cache_reuse": same_gbs / HBM_PEAK_GBS, "avg_launch_ms_cache_reuse": same_ms,
+                     "copy_probe_gbs": probe["gbs"]},
+        "codec_form": {"kernels": "fwd2d then zonal_recon", "ms_per_r": codec_ms,
+                       "bytes_per_tile_moved": moved, "frac": moved * ntiles / (codec_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                       "bytes_per_tile_int32_codec": 2560,
+                       "frac_int32_codec_basis": 2560 * ntiles / (codec_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "kernels_ms": {f"encode_zonal_r{r}": enc_ms[r] for r in RS},
         "two_kernel_path": {
             "fwd2d_ms": fwd_ms, "fwd2d_gbs": FWD_BYTES_PER_TILE * ntiles / (fwd_ms * 1e-3) / 1e9,
-            **{f"zonal_recon_r{r}_ms": two[r][1] for r in RS},
-            **{f"zonal_recon_r{r}_gbs": recon_bytes_per_tile(r) * ntiles / (two[r][1] * 1e-3) / 1e9 for r in RS}},
+            **{f"zonal_recon_r{r}_ms": rec_ms[r] for r in RS},
+            **{f"zonal_recon_r{r}_gbs": recon_bytes_per_tile(r) * ntiles / (rec_ms[r] * 1e-3) / 1e9 for r in RS}},
         "psnr_db_mean": psnr,
         "input_gen_s": gen_s,
     }
+    del copies
+    torch.cuda.empty_cache()
     if not args.no_other:
         t0 = time.perf_counter()
         zz = image_experiment(torch, adct, stream, x, coef, out, n_img)
@@ -549,10 +602,23 @@ def main():
             other[name]["wall_s"] = time.perf_counter() - t0
             torch.cuda.empty_cache()
             print(f"[bench] {name} done in {other[name]['wall_s']:.1f} s", file=sys.stderr, flush=True)
-        result["other_workloads"] = other
+        full["other_workloads"] = other
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(img)
-    print(json.dumps(result), flush=True)
+        full["cpu_baseline"] = cpu_baseline(img)
+    try:
+        import psutil
+        full["child_processes_at_end"] = len(psutil.Process().children(recursive=True))
+    except Exception:  # psutil is optional
+        pass
+    path = args.detail
+    try:
+        os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+        with open(path, "w") as f:
+            json.dump(full, f)
+        full["detail_file"] = os.path.relpath(os.path.abspath(path), ROOT)
+    except OSError as err:
+        print(f"[bench] detail file not written: {err}", file=sys.stderr, flush=True)
+    print(json.dumps(summary_line(full)), flush=True)
 
 
 if __name__ == "__main__":

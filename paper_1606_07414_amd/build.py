@@ -14,11 +14,12 @@ SOURCES = ["adct_host.cpp", "adct_plain.hip", "adct_batch.hip", "adct_server.hip
            "adct_t8.hip", "adct_compare.hip", "adct_mixed.hip", "adct_sync.hip"]
 
 HIPCC_FLAGS = [
-    "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
+    "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
     # packed-FP32 instructions are kept out of generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-pthread",
 ]
+OBJ_DIR = os.path.join(PKG, "_build")
 
 
 def sources() -> list[str]:
@@ -26,11 +27,25 @@ def sources() -> list[str]:
 
 
 def build(verbose: bool = False) -> str:
-    """Compile every source into libadct.so next to this file; returns its path."""
+    """Compile every source (in parallel, one object each) and link them into
+    libadct.so next to this file; returns its path."""
+    from concurrent.futures import ThreadPoolExecutor
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    os.makedirs(OBJ_DIR, exist_ok=True)
+    objs = [os.path.join(OBJ_DIR, os.path.basename(s) + ".o") for s in sources()]
+
+    def compile_one(src_obj):
+        src, obj = src_obj
+        cmd = [hipcc, *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-c", src, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd)
+
+    jobs = max(1, min(len(objs), int(os.environ.get("MAX_JOBS", "0")) or (os.cpu_count() or 1)))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        list(ex.map(compile_one, zip(sources(), objs)))
     tmp = LIB + ".tmp"
-    cmd = [hipcc, *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-           *sources(), "-o", tmp]
+    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
