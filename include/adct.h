@@ -126,6 +126,14 @@ int adct_psnr(const int64_t* sse, int32_t n, double pixels_per_image, double pea
  * in16, out16: host int32[16]; ADCT_E_ARG for another `which`. */
 int adct_host_butterfly(int32_t which, const int32_t* in16, int32_t* out16);
 
+/* The same butterflies as adct_host_butterfly (same `which`), run on the
+ * host with a value type that counts every addition and subtraction it
+ * takes part in and defines no other arithmetic: *additions receives the
+ * count for the whole call (Table 1: 44 for T and for T^T by the Section 2.2
+ * factorisation, 64 for the WHT; the T8 modes transform both halves, 2 x 14).
+ * ADCT_E_ARG for a NULL pointer, another `which`, or a result outside int32. */
+int adct_host_butterfly_count(int32_t which, const int32_t* in16, int32_t* out16, int64_t* additions);
+
 /* ---- plain device calls -------------------------------------------------- */
 
 /* Forward transform Y = T A T^T of every 16x16 block of `src` (Section 3.1;

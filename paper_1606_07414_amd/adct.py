@@ -88,6 +88,7 @@ _SIGNATURES = {
     "adct_quant_tables": (ctypes.c_int, [ctypes.c_int, _P, _P]),
     "adct_psnr": (ctypes.c_int, [_P, _I32, _D, _D, _P]),
     "adct_host_butterfly": (ctypes.c_int, [_I32, _P, _P]),
+    "adct_host_butterfly_count": (ctypes.c_int, [_I32, _P, _P, ctypes.POINTER(_I64)]),
     "adct_fwd2d": (ctypes.c_int, [_PP, _P, _P]),
     "adct_inv2d": (ctypes.c_int, [_P, _I64, _P, _P]),
     "adct_scale": (ctypes.c_int, [_P, _I64, _P, _P]),
@@ -264,6 +265,18 @@ def host_butterfly(x, inverse: bool = False, wht: bool = False, t8_halves: bool 
         which = 2 if wht else (1 if inverse else 0)
     _check(_lib().adct_host_butterfly(which, x.ctypes.data, y.ctypes.data), "host_butterfly")
     return y
+
+
+def host_butterfly_count(x, inverse: bool = False, wht: bool = False, t8_halves: bool = False):
+    """(output, additions): the kernels' butterfly on the host, with every
+    addition and subtraction it makes counted."""
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.int32).reshape(16))
+    y = np.empty(16, np.int32)
+    which = (4 if inverse else 3) if t8_halves else (2 if wht else (1 if inverse else 0))
+    n = _I64(0)
+    _check(_lib().adct_host_butterfly_count(which, x.ctypes.data, y.ctypes.data, ctypes.byref(n)),
+           "host_butterfly_count")
+    return y, n.value
 
 
 # ---------------------------------------------------------------- device calls

@@ -72,6 +72,24 @@ int class_of(int u, int v) {
     return lu + lv - 4;
 }
 
+// An integer that counts the additions and subtractions made with it.  It
+// defines no other arithmetic, so a butterfly instantiated with it compiles
+// only if its dataflow is additions and subtractions alone (no negation,
+// multiply or shift).
+struct CountedInt {
+    int64_t v = 0;
+    static thread_local int64_t ops;
+};
+thread_local int64_t CountedInt::ops = 0;
+inline CountedInt operator+(CountedInt a, CountedInt b) {
+    ++CountedInt::ops;
+    return CountedInt{a.v + b.v};
+}
+inline CountedInt operator-(CountedInt a, CountedInt b) {
+    ++CountedInt::ops;
+    return CountedInt{a.v - b.v};
+}
+
 }  // namespace adct
 
 using namespace adct;
@@ -188,6 +206,35 @@ int adct_work_queue(const int64_t* tiles_per_job, int32_t njobs, int32_t tiles_p
 
 // Host execution of the kernels' 1D butterflies (the same code the GPU
 // runs), for checking the dataflow without a GPU.
+int adct_host_butterfly_count(int32_t which, const int32_t* in16, int32_t* out16, int64_t* additions) {
+    if (!in16 || !out16 || !additions || which < 0 || which > 4) return ADCT_E_ARG;
+    CountedInt x[16], y[16];
+    CountedInt::ops = 0;
+    for (int i = 0; i < 16; ++i) x[i].v = in16[i];
+    if (which >= 3) {
+        for (int h = 0; h < 2; ++h) {
+            CountedInt a[8], b[8];
+            for (int i = 0; i < 8; ++i) a[i] = x[8 * h + i];
+            if (which == 3)
+                fwd8(a, b);
+            else
+                inv8(a, b);
+            for (int i = 0; i < 8; ++i) y[8 * h + i] = b[i];
+        }
+    } else if (which == 2)
+        wht16(x, y);
+    else if (which == 1)
+        inv16(x, y);
+    else
+        fwd16(x, y);
+    for (int i = 0; i < 16; ++i) {
+        if (y[i].v < INT32_MIN || y[i].v > INT32_MAX) return ADCT_E_ARG;
+        out16[i] = (int32_t)y[i].v;
+    }
+    *additions = CountedInt::ops;
+    return ADCT_OK;
+}
+
 int adct_host_butterfly(int32_t which, const int32_t* in16, int32_t* out16) {
     if (!in16 || !out16 || which < 0 || which > 4) return ADCT_E_ARG;
     int32_t x[16], y[16];

@@ -108,6 +108,29 @@ def test_kernel_butterflies_on_host_basis_and_random():
         assert np.array_equal(adct.host_butterfly(x, inverse=True), T.T @ x)
 
 
+def test_kernel_butterflies_count_the_paper_additions(golden_dir):
+    """The kernels' own dataflows (the templates the GPU instantiates), run
+    with a value type that counts additions: Table 1's 44 for T (and its
+    transpose), 64 for the WHT, Section 2.1's 14 for T8 (per half)."""
+    import json
+    import os
+    tab = json.load(open(os.path.join(golden_dir, "table1_complexity.json")))
+    T = O.transform_matrix()
+    rng = np.random.default_rng(44)
+    for x in rng.integers(-(1 << 20), 1 << 20, size=(50, 16)):
+        y, n = adct.host_butterfly_count(x)
+        assert n == tab["proposed"]["add"] == 44 and np.array_equal(y, T @ x)
+        y, n = adct.host_butterfly_count(x, inverse=True)
+        assert n == 44 and np.array_equal(y, T.T @ x)
+        y, n = adct.host_butterfly_count(x, wht=True)
+        assert n == tab["competitor_additions"]["wht"]
+        for inv in (False, True):
+            y, n = adct.host_butterfly_count(x, inverse=inv, t8_halves=True)
+            assert n == 2 * tab["t8_additions"]
+            assert np.array_equal(y, adct.host_butterfly(x, inverse=inv, t8_halves=True))
+    assert adct.lib().adct_host_butterfly_count(5, FAKE, FAKE, None) == adct.E_ARG
+
+
 def test_psnr_host():
     out = adct.psnr([0, 100, 256], 100)
     assert out[0] == math.inf
