@@ -226,12 +226,19 @@ __global__ __launch_bounds__(kServeTPW * 8) void k_serve(ServeArgs s) {
         __syncthreads();  // the previous item is finished with LDS and sh_*
         if (tid == 0) {
             uint32_t j = max(sh_cursor, load_sys(s.low));
-            // acquire: the descriptors of slots below the count, which the
-            // dispatcher stored before advancing it, are read after it
-            const uint32_t cnt = __hip_atomic_load(s.count, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+            // A relaxed poll: an acquire here would invalidate this XCD's L2
+            // on every poll of every idle workgroup, which costs the working
+            // ones their cached staging.  The scan needs no ordering: each
+            // slot's item count is written once, over the zero the ring was
+            // cleared to at create (a published request has at least one
+            // item), so the count read is either 0 -- not visible yet: stop
+            // and poll again, claiming nothing -- or the published one.  The
+            // rest of a descriptor is read after an acquire fence (below).
+            const uint32_t cnt = load_sys(s.count);
             uint32_t res_j = 0xffffffffu, res_g = 0;
             while (j < cnt) {
                 const uint32_t n = load_sys(&s.desc[j].nitems);
+                if (n == 0u) break;
                 const uint32_t g = atomicAdd(s.claim + j, 1u);
                 if (g < n) {
                     res_j = j;
