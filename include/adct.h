@@ -422,6 +422,31 @@ int adct_batch_info(const adct_batch* b, int64_t* tiles, int64_t* items, adct_tu
 /* Releases the batch (synchronises its last submission first). */
 int adct_batch_destroy(adct_batch* b);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one uneven
+ * batch coded like adct_batch_create + adct_batch_submit + adct_batch_destroy,
+ * with identical results, but with no allocation and no graph.  The job
+ * table, the work queue and the queue heads go into a static device array of
+ * ADCT_NOALLOC_SCRATCH_BYTES that the library's code object holds on every
+ * device it is loaded on, until the process ends; its address is looked up
+ * once per device, on the first call there.  The host builds the queue and
+ * copies the table and queue into the array with hipMemcpyAsync on `stream`
+ * from host memory that it frees on return (HIP completes copies from
+ * pageable memory before returning, so the call may wait for earlier work
+ * on `stream`), then launches the reset kernel (queue heads and every job's
+ * SSE cleared) and the persistent kernel on `stream` (current device).  The
+ * caller's buffers must stay valid until the stream has run the launch.
+ * Every call on one device shares that device's array and leaves the last
+ * call's contents in it: calls that overlap on one device (different streams,
+ * or host threads racing on one stream) race and give undefined results.
+ * ADCT_E_TOO_LARGE when the table and queue exceed the array (fewer, larger
+ * items -- a larger tiles_per_group * groups_per_item -- need less);
+ * validation errors as adct_batch_create; nothing is launched on error.
+ * `tune` NULL = adct_default_tune. */
+#define ADCT_NOALLOC_SCRATCH_BYTES (16u << 20)
+int adct_batch_run_noalloc(const adct_job* jobs, int32_t njobs, int32_t op, int32_t param, const adct_tune* tune,
+                           void* stream);
+
 /* Chooses a tuning for (op, param, these jobs) by timing every candidate
  * (tiles_per_group x groups_per_item x wgs_per_cu) `reps` times on the jobs
  * themselves -- their dst, coef and sse buffers are overwritten -- and keeps

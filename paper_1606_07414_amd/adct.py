@@ -124,6 +124,7 @@ _SIGNATURES = {
     "adct_batch_submit": (ctypes.c_int, [_P, _P]),
     "adct_batch_info": (ctypes.c_int, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(Tune)]),
     "adct_batch_destroy": (ctypes.c_int, [_P]),
+    "adct_batch_run_noalloc": (ctypes.c_int, [ctypes.POINTER(Job), _I32, _I32, _I32, ctypes.POINTER(Tune), _P]),
     "adct_autotune": (ctypes.c_int, [_I32, _I32, ctypes.POINTER(Job), _I32, ctypes.c_char_p, _I32,
                                      ctypes.POINTER(Tune), ctypes.POINTER(_D)]),
     "adct_now_ns": (ctypes.c_int64, []),
@@ -607,6 +608,21 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def batch_run_noalloc(srcs, dsts, op: int, param: int, coefs=None, sses=None, tune: Tune | None = None,
+                      stream=None):
+    """One uneven batch coded without any device allocation: the job table
+    and work queue live in the library's fixed device array (shared by every
+    call on the device; calls must not overlap).  Asynchronous on `stream`:
+    the tensors must stay alive until the stream has run it."""
+    jobs = make_jobs(srcs, dsts, coefs, sses)
+    _check(_lib().adct_batch_run_noalloc(jobs, len(jobs), op, param,
+                                         ctypes.byref(tune) if tune is not None else None, _stream(stream)),
+           "batch_run_noalloc")
+
+
+NOALLOC_SCRATCH_BYTES = 16 << 20  # ADCT_NOALLOC_SCRATCH_BYTES
 
 
 def autotune(srcs, dsts, op: int, param: int, coefs=None, sses=None, cache_path=None, reps: int = 3):

@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -271,6 +272,34 @@ int upload(const std::vector<T>& h, T** d) {
     return ADCT_OK;
 }
 
+// Device memory of adct_batch_run_noalloc: queue heads, job table and work
+// queue.  Host code never passes the array's name to a kernel or a copy: in
+// host code it is a stand-in, and its device address (one per device) comes
+// from hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[ADCT_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept.
+int scratch_ptr(unsigned char** out) {
+    static std::mutex mu;
+    static unsigned char* ptrs[kMaxDevices] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return ADCT_E_HIP;
+    if (dev < 0 || dev >= kMaxDevices) return ADCT_E_HIP;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptrs[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return ADCT_E_HIP;
+        ptrs[dev] = static_cast<unsigned char*>(p);
+    }
+    *out = ptrs[dev];
+    return ADCT_OK;
+}
+
+constexpr size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
+
 }  // namespace
 }  // namespace adct
 
@@ -400,6 +429,61 @@ int adct_batch_submit(adct_batch* b, void* stream) {
     if (hipGraphLaunch(b->exec, s) != hipSuccess) return ADCT_E_HIP;
     if (hipEventRecord(b->done, s) != hipSuccess) return ADCT_E_HIP;
     return ADCT_OK;
+}
+
+int adct_batch_run_noalloc(const adct_job* jobs, int32_t njobs, int32_t op, int32_t param, const adct_tune* tune,
+                           void* stream) {
+    std::vector<GroupArgs> args;
+    std::vector<int64_t> tiles;
+    int dtype = 0;
+    int rc = make_job_args(jobs, njobs, op, param, args, tiles, dtype);
+    if (rc) return rc;
+    adct_tune t;
+    if (tune)
+        t = *tune;
+    else
+        adct_default_tune(&t);
+    if (!tune_valid(t)) return ADCT_E_ARG;
+    std::vector<uint32_t> items;
+    int64_t n_items = 0;
+    if ((rc = build_items(tiles, t, items, n_items))) return rc;
+    // layout of the array: heads, job table, items (each 256-byte aligned)
+    const size_t heads_bytes = align256(kQueues * kHeadStride * sizeof(uint32_t));
+    const size_t jobs_bytes = align256(args.size() * sizeof(GroupArgs));
+    const size_t items_bytes = (size_t)n_items * sizeof(ItemDev);
+    if (heads_bytes + jobs_bytes + items_bytes > (size_t)ADCT_NOALLOC_SCRATCH_BYTES) return ADCT_E_TOO_LARGE;
+    int cus = 0;
+    if ((rc = cu_count(&cus, nullptr))) return rc;
+    unsigned char* base = nullptr;
+    if ((rc = scratch_ptr(&base))) return rc;
+    std::vector<ItemDev> it((size_t)n_items);
+    for (int64_t i = 0; i < n_items; ++i) it[(size_t)i] = ItemDev{items[3 * i], items[3 * i + 1], items[3 * i + 2]};
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    GroupArgs* d_jobs = reinterpret_cast<GroupArgs*>(base + heads_bytes);
+    ItemDev* d_items = reinterpret_cast<ItemDev*>(base + heads_bytes + jobs_bytes);
+    if (hipMemcpyAsync(d_jobs, args.data(), args.size() * sizeof(GroupArgs), hipMemcpyHostToDevice, s) !=
+        hipSuccess)
+        return ADCT_E_HIP;
+    if (items_bytes &&
+        hipMemcpyAsync(d_items, it.data(), items_bytes, hipMemcpyHostToDevice, s) != hipSuccess)
+        return ADCT_E_HIP;
+    adct_batch b{};
+    b.op = op;
+    b.param = param;
+    b.dtype = dtype;
+    b.tune = t;
+    b.n_items = n_items;
+    b.njobs = (uint32_t)args.size();
+    b.grid = (unsigned)(cus * t.wgs_per_cu);
+    b.d_jobs = d_jobs;
+    b.d_items = d_items;
+    b.d_heads = reinterpret_cast<uint32_t*>(base);
+    rc = record_launch(&b, s);
+    // the object only carried the launch parameters: nothing of it is owned
+    b.d_jobs = nullptr;
+    b.d_items = nullptr;
+    b.d_heads = nullptr;
+    return rc;
 }
 
 int adct_batch_info(const adct_batch* b, int64_t* tiles, int64_t* items, adct_tune* tune) {

@@ -417,3 +417,11 @@ def test_mixed_argument_checks():
     assert f(ctypes.byref(p), 27, 5, None, None, ctypes.byref(p), 32, FAKE + 4, None) == adct.E_ALIGN
     bad = _plane(FAKE, adct.I16, 32, 40, 96)
     assert f(ctypes.byref(bad), 27, 5, None, None, ctypes.byref(bad), 32, None, None) == adct.E_SHAPE
+
+
+def test_noalloc_scratch_size_matches_header():
+    import re
+    with open(os.path.join(ROOT, "include", "adct.h")) as f:
+        m = re.search(r"#define ADCT_NOALLOC_SCRATCH_BYTES \((\d+)u << (\d+)\)", f.read())
+    assert m, "ADCT_NOALLOC_SCRATCH_BYTES not found"
+    assert adct.NOALLOC_SCRATCH_BYTES == int(m.group(1)) << int(m.group(2))
