@@ -52,6 +52,9 @@ ENC_SOURCES = ("adct_butterfly.hpp", "adct_tile.hpp", "adct_core.hpp", "adct_pla
                "adct_round.hpp")
 SERVE_TILES_PER_ITEM = 0     # persistent server: tiles per work item (0: chosen per request)
 SERVE_WGS_PER_CU = 2         # persistent server: loop workgroups per CU
+SERVE_DMA_MIN = 0            # persistent server: DMA copy from this many pixels (0: the library default)
+CAPACITY_RATES = (5000, 7500, 10000, 15000, 20000)   # req/s, for the capacity search
+CAPACITY_P99_MS = 1.0
 
 
 def recon_bytes_per_tile(r: int) -> int:
@@ -311,11 +314,40 @@ def uneven_batch(torch, adct, stream, n=4096):
     return out
 
 
+def serve_run(adct, mode, views, arr, tiles, warm):
+    """One server, every request replayed at its arrival time: p50 / p99 /
+    mean latency (arrival to observed completion) and tiles/s from the first
+    counted arrival to the last completion, the first `warm` discarded."""
+    n_req = len(views)
+    srv = adct.Server(pool_bytes=16 << 30, qp=27, mode=mode, max_inflight=512, max_requests=n_req,
+                      auto_release=True, tiles_per_item=SERVE_TILES_PER_ITEM, wgs_per_cu=SERVE_WGS_PER_CU,
+                      dma_min_pixels=SERVE_DMA_MIN if mode == adct.SERVE_PERSISTENT else 0)
+    t0 = adct.now_ns() + 20_000_000
+    tickets = [srv.submit(v, t0 + int(a * 1e9)) for v, a in zip(views, arr)]
+    srv.wait_all(600)
+    lat, first, last = [], None, None
+    for k, t in enumerate(tickets):
+        rc, r = srv.poll(t)
+        if k < warm:
+            continue
+        lat.append((r.t_done_ns - r.t_arrival_ns) * 1e-6)
+        first = r.t_arrival_ns if first is None else min(first, r.t_arrival_ns)
+        last = r.t_done_ns if last is None else max(last, r.t_done_ns)
+    st = srv.stats()
+    srv.close()
+    return {"p50_ms": adct.percentile(lat, 50), "p99_ms": adct.percentile(lat, 99), "mean_ms": float(np.mean(lat)),
+            "tiles_per_s": float(tiles[warm:].sum() / ((last - first) * 1e-9)),
+            "loop_launches": st["loop_launches"], "pool_high_water": st["pool_high_water"]}
+
+
 def serving(torch, adct, n_req, rates=(200, 500, 1000, 2000, 5000), warm=100):
     """Poisson arrivals of uint8 AR(1) requests with sides log-uniform in
     [256, 4096]; fwd + quant (QP 27) + dequant + inverse kept on the device.
     The continuous-batching server against the plain per-request launch;
-    latency = arrival to observed completion, the first `warm` discarded."""
+    latency = arrival to observed completion, the first `warm` discarded.
+    Capacity: per mode, the highest rate of CAPACITY_RATES whose p99 stays
+    within CAPACITY_P99_MS (its served tiles/s), and the rate at which an
+    all-at-once burst of the same requests is served."""
     import synth
     side_pool = 4096
     pool = np.stack([synth.ar1_image(synth.SEED_REQ_CONTENT + i, side_pool, side_pool) for i in range(4)])
@@ -337,31 +369,27 @@ def serving(torch, adct, n_req, rates=(200, 500, 1000, 2000, 5000), warm=100):
         ms = timed(torch, lambda: dst.copy_(big, non_blocking=True), 10, cs)
     out = {"requests": n_req, "warmup_discarded": warm, "mean_tiles_per_request": float(tiles.mean()),
            "h2d_gbs_pinned": big.numel() / (ms * 1e-3) / 1e9, "tiles_per_item": SERVE_TILES_PER_ITEM,
-           "wgs_per_cu": SERVE_WGS_PER_CU, "rate": {}}
+           "wgs_per_cu": SERVE_WGS_PER_CU, "dma_min_pixels": SERVE_DMA_MIN, "rate": {}}
+    modes = (("persistent", adct.SERVE_PERSISTENT), ("plain", adct.SERVE_PLAIN))
     for lam in rates:
         arr = synth.poisson_arrivals(float(lam), n_req)
-        row = {}
-        for name, mode in (("persistent", adct.SERVE_PERSISTENT), ("plain", adct.SERVE_PLAIN)):
-            srv = adct.Server(pool_bytes=16 << 30, qp=27, mode=mode, max_inflight=512, max_requests=n_req,
-                              auto_release=True, tiles_per_item=SERVE_TILES_PER_ITEM, wgs_per_cu=SERVE_WGS_PER_CU)
-            t0 = adct.now_ns() + 20_000_000
-            tickets = [srv.submit(v, t0 + int(a * 1e9)) for v, a in zip(views, arr)]
-            srv.wait_all(600)
-            lat, first, last = [], None, None
-            for k, t in enumerate(tickets):
-                rc, r = srv.poll(t)
-                if k < warm:
-                    continue
-                lat.append((r.t_done_ns - r.t_arrival_ns) * 1e-6)
-                first = r.t_arrival_ns if first is None else min(first, r.t_arrival_ns)
-                last = r.t_done_ns if last is None else max(last, r.t_done_ns)
-            st = srv.stats()
-            srv.close()
-            row[name] = {"p50_ms": adct.percentile(lat, 50), "p99_ms": adct.percentile(lat, 99),
-                         "mean_ms": float(np.mean(lat)),
-                         "tiles_per_s": float(tiles[warm:].sum() / ((last - first) * 1e-9)),
-                         "loop_launches": st["loop_launches"], "pool_high_water": st["pool_high_water"]}
-        out["rate"][lam] = row
+        out["rate"][lam] = {name: serve_run(adct, mode, views, arr, tiles, warm) for name, mode in modes}
+    # capacity: rates above the curve until p99 passes the bound, and a burst
+    cap = {}
+    for name, mode in modes:
+        best, tried = None, {}
+        for lam in CAPACITY_RATES:
+            r = out["rate"][lam][name] if lam in out["rate"] else \
+                serve_run(adct, mode, views, synth.poisson_arrivals(float(lam), n_req), tiles, warm)
+            tried[lam] = {"p50_ms": r["p50_ms"], "p99_ms": r["p99_ms"], "tiles_per_s": r["tiles_per_s"]}
+            if r["p99_ms"] > CAPACITY_P99_MS:
+                break
+            best = lam
+        burst = serve_run(adct, mode, views, np.zeros(n_req), tiles, warm)
+        cap[name] = {"max_rate_p99_within_bound": best, "p99_bound_ms": CAPACITY_P99_MS,
+                     "tiles_per_s": tried[best]["tiles_per_s"] if best else None, "tried": tried,
+                     "burst_tiles_per_s": burst["tiles_per_s"], "burst_p99_ms": burst["p99_ms"]}
+    out["capacity"] = cap
     return out
 
 
@@ -439,7 +467,10 @@ def summary_line(full: dict) -> dict:
                 str(lam): {m: [round(row[m]["p50_ms"], 3), round(row[m]["p99_ms"], 3)] for m in row}
                 for lam, row in sv["rate"].items()}
             if "capacity" in sv:
-                summ["serving_capacity_tiles_per_s"] = {m: c["tiles_per_s"] for m, c in sv["capacity"].items()}
+                summ["serving_capacity"] = {m: {"max_req_per_s_p99_le_1ms": c["max_rate_p99_within_bound"],
+                                                "tiles_per_s": c["tiles_per_s"],
+                                                "burst_tiles_per_s": round(c["burst_tiles_per_s"])}
+                                            for m, c in sv["capacity"].items()}
         zz = other.get("image_experiment_zigzag_1024x512x512")
         if zz:
             summ["zigzag_psnr_db"] = {str(r): round(v["psnr_db"], 2) for r, v in zz["r"].items() if r in (10, 45, 150)}

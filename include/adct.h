@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define ADCT_ABI_VERSION 1
+#define ADCT_ABI_VERSION 2
 
 /* ---- status codes ---------------------------------------------------- */
 #define ADCT_OK            0
@@ -468,10 +468,13 @@ int adct_autotune(int32_t op, int32_t param, const adct_job* jobs, int32_t njobs
  * kernel forwards new requests to its other workgroups, which claim work
  * items (runs of tiles of one request) as they appear, copy each item's
  * pixel rows from the caller's pinned host memory into the pool in long
- * contiguous runs and code them from there (no copy ahead, no other
- * stream), so requests that arrive while others run are coded alongside
- * them; the last workgroup to finish a request posts its SSE and a
- * completion flag to host memory.  In ADCT_SERVE_PLAIN mode the same
+ * contiguous runs and code them from there, so requests that arrive while
+ * others run are coded alongside them; the last workgroup to finish a
+ * request posts its SSE and a completion flag to host memory.  Requests of
+ * at least dma_min_pixels pixels are instead copied into the pool by the
+ * DMA engine, on a second stream, and published once that copy is done
+ * (the engine moves a large request over the host link faster than the
+ * loop's own reads, which then code).  In ADCT_SERVE_PLAIN mode the same
  * admission feeds a plain per-request path instead (one stream, first in
  * first out: copy in, adct_fwd2d_quant, adct_dequant_recon, SSE copy back,
  * event), the baseline the persistent loop is measured against.  In both
@@ -503,7 +506,16 @@ typedef struct adct_server_cfg {
                                 dispatching wave (about 1-2 us each) before the
                                 loop ends; the server relaunches it when work
                                 reappears (0 = 100000)                           */
+    int32_t dma_min_pixels;  /* persistent: requests of at least this many
+                                pixels are copied into the pool by the DMA
+                                engine (one copy on a second stream) and
+                                published to the loop once the copy is done;
+                                smaller ones are staged by the loop itself.
+                                0 = ADCT_SERVE_DMA_MIN_DEFAULT, -1 = never       */
+    int32_t reserved;
 } adct_server_cfg;
+
+#define ADCT_SERVE_DMA_MIN_DEFAULT (2048 * 2048)
 
 typedef struct adct_result {
     int32_t status;          /* ADCT_OK, ADCT_PENDING or ADCT_E_STOPPED          */

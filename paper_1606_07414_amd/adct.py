@@ -55,7 +55,8 @@ class ServerCfg(ctypes.Structure):
     _fields_ = [("pool_bytes", ctypes.c_int64), ("qp", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("max_inflight", ctypes.c_int32), ("max_requests", ctypes.c_int32),
                 ("auto_release", ctypes.c_int32), ("tiles_per_item", ctypes.c_int32),
-                ("wgs_per_cu", ctypes.c_int32), ("idle_polls", ctypes.c_int32)]
+                ("wgs_per_cu", ctypes.c_int32), ("idle_polls", ctypes.c_int32),
+                ("dma_min_pixels", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Result(ctypes.Structure):
@@ -646,9 +647,9 @@ class Server:
 
     def __init__(self, pool_bytes: int, qp: int = 27, mode: int = SERVE_PERSISTENT, max_inflight: int = 64,
                  max_requests: int = 4096, auto_release: bool = False, tiles_per_item: int = 0,
-                 wgs_per_cu: int = 0, idle_polls: int = 0):
+                 wgs_per_cu: int = 0, idle_polls: int = 0, dma_min_pixels: int = 0):
         cfg = ServerCfg(pool_bytes, qp, mode, max_inflight, max_requests, 1 if auto_release else 0, tiles_per_item,
-                        wgs_per_cu, idle_polls)
+                        wgs_per_cu, idle_polls, dma_min_pixels, 0)
         h = _P()
         _check(_lib().adct_server_create(ctypes.byref(h), ctypes.byref(cfg)), "server_create")
         self._h = h

@@ -9,11 +9,14 @@
 // stores j + 1 to a host-mapped slot count (release order).  The loop takes
 // the pixels straight from the caller's pinned host memory: every work item
 // first copies its own sample rows over the host link into the request's
-// pool block, in long contiguous runs, and is then coded from there, so
-// nothing is copied ahead and no other stream is involved.  Items are staged
-// in slot order, at most kStagers at a time, and the coding of one item
-// overlaps the transfer of others.  Results (levels and reconstruction) go
-// to the request's block of the device pool.
+// pool block, in long contiguous runs, and is then coded from there.  Items
+// are staged in slot order, at most kStagers at a time, and the coding of
+// one item overlaps the transfer of others.  A large request (at least
+// dma_min_pixels) is instead copied into its pool block by the DMA engine on
+// a second stream and published, with no host address, once the host sees
+// that copy's event: the engine moves long transfers over the link faster
+// than the loop's reads do.  Results (levels and reconstruction) go to the
+// request's block of the device pool.
 //
 // Loop kernel (persistent).  Workgroup 0 is the dispatcher: one wave polls
 // the host-mapped slot count, copies new descriptors into device memory and
@@ -290,19 +293,25 @@ __global__ __launch_bounds__(kServeTPW * 8) void k_serve(ServeArgs s) {
         // order, so the items of earlier slots are all held by workers that
         // are not waiting here: the lowest such slot always progresses.
         // At most kStagers items are staged at one time (tickets in order).
-        if (tid == 0) {
-            while (load_sys(s.stage_low) < j) __builtin_amdgcn_s_sleep(2);
-            const uint32_t ticket = atomicAdd(s.stage_next, 1u);
-            while (load_sys(s.stage_done) + kStagers <= ticket) __builtin_amdgcn_s_sleep(1);
+        // A request whose samples the DMA engine has already copied into the
+        // pool (no host address in its descriptor) only counts as staged.
+        const uint64_t hsrc = rfl64(sh_desc[10]);
+        if (hsrc) {
+            if (tid == 0) {
+                while (load_sys(s.stage_low) < j) __builtin_amdgcn_s_sleep(2);
+                const uint32_t ticket = atomicAdd(s.stage_next, 1u);
+                while (load_sys(s.stage_done) + kStagers <= ticket) __builtin_amdgcn_s_sleep(1);
+            }
+            __syncthreads();
+            // the item's samples into the pool first (before the group
+            // arguments are formed, which keeps fewer scalar values live
+            // across the copy)
+            stage_item(global_ptr(hsrc), rfl(dw[22]), global_ptr(rfl64(sh_desc[0])), rfl(dw[19]), rfl(dw[10]),
+                       FastDiv{rfl(dw[11]), rfl(dw[12]), rfl(dw[13])}, t0, gend);
+            __syncthreads();
         }
-        __syncthreads();
-        // the item's samples into the pool first (before the group arguments
-        // are formed, which keeps fewer scalar values live across the copy)
-        stage_item(global_ptr(rfl64(sh_desc[10])), rfl(dw[22]), global_ptr(rfl64(sh_desc[0])), rfl(dw[19]),
-                   rfl(dw[10]), FastDiv{rfl(dw[11]), rfl(dw[12]), rfl(dw[13])}, t0, gend);
-        __syncthreads();
         if (tid == 0) {
-            atomicAdd(s.stage_done, 1u);
+            if (hsrc) atomicAdd(s.stage_done, 1u);
             if (atomicAdd(s.staged + j, 1u) + 1u == nitems) atomicMax(s.stage_low, j + 1u);
         }
         const GroupArgs a = args_from_desc(sh_desc, s, j);
@@ -352,7 +361,8 @@ struct Req {
     int64_t off = -1;
     int64_t sse = -1;
     int state = kWaiting;
-    int ev = -1;  // plain: event slot marking the end of the request
+    int ev = -1;  // plain: event slot marking the end of the request;
+                  // persistent: event slot marking the end of its DMA copy
 };
 
 // Pool block of a request: the copied source, the reconstruction and the
@@ -395,6 +405,8 @@ struct adct_server {
     std::vector<hipEvent_t> events;
     std::vector<int> free_events;
     // persistent mode
+    hipStream_t copy_stream = nullptr; // DMA copies of large requests
+    std::vector<int64_t> dma_pending; // copies issued, not yet published (issue order)
     ReqDesc* h_desc = nullptr;        // host-mapped descriptor ring, by slot
     ReqDesc* d_hdesc = nullptr;       // its device address
     uint32_t* h_count = nullptr;      // host-mapped slot count
@@ -495,18 +507,27 @@ int64_t block_bytes(int32_t h, int32_t w) {
     return 2 * Pool::round_up(plane) + 2 * plane;
 }
 
+// Copies a request's pixels into its pool block on `stream` (rows packed).
+void copy_in(adct_server* S, const Req& r, const Block& b, hipStream_t stream) {
+    if (r.pitch == r.w)
+        hip_ok(S, hipMemcpyAsync(b.src, r.host, (size_t)((int64_t)r.h * r.w), hipMemcpyHostToDevice, stream));
+    else
+        hip_ok(S, hipMemcpy2DAsync(b.src, (size_t)r.w, r.host, (size_t)r.pitch, (size_t)r.w, (size_t)r.h,
+                                   hipMemcpyHostToDevice, stream));
+}
+
+bool event_done(adct_server* S, int ev);
+void publish(adct_server* S, int64_t k, uint64_t hsrc);
+
 // Hands an admitted request to the device (called with mu held).  Persistent
-// mode: publish its descriptor; plain mode: copy in, code, copy the SSE back
-// and record an event, all on the one stream.
+// mode: publish its descriptor, or for a large request start its DMA copy
+// into the pool (published when done); plain mode: copy in, code, copy the
+// SSE back and record an event, all on the one stream.
 void issue(adct_server* S, int64_t k) {
     Req& r = S->reqs[(size_t)k];
     const Block b = block_of(S, r);
     if (S->cfg.mode == ADCT_SERVE_PLAIN) {
-        if (r.pitch == r.w)
-            hip_ok(S, hipMemcpyAsync(b.src, r.host, (size_t)((int64_t)r.h * r.w), hipMemcpyHostToDevice, S->stream));
-        else
-            hip_ok(S, hipMemcpy2DAsync(b.src, (size_t)r.w, r.host, (size_t)r.pitch, (size_t)r.w, (size_t)r.h,
-                                       hipMemcpyHostToDevice, S->stream));
+        copy_in(S, r, b, S->stream);
         adct_plane ps{b.src, ADCT_U8, r.h, r.w, 0, r.w};
         adct_plane pd{b.dst, ADCT_U8, r.h, r.w, 0, r.w};
         int rc = adct_fwd2d_quant(&ps, S->cfg.qp, reinterpret_cast<int16_t*>(b.q), S->stream);
@@ -519,11 +540,31 @@ void issue(adct_server* S, int64_t k) {
         r.ev = S->free_events.back();
         S->free_events.pop_back();
         hip_ok(S, hipEventRecord(S->events[(size_t)r.ev], S->stream));
+    } else if (S->cfg.dma_min_pixels > 0 && (int64_t)r.h * r.w >= S->cfg.dma_min_pixels) {
+        // the DMA engine copies it into the pool; published when done
+        copy_in(S, r, b, S->copy_stream);
+        r.ev = S->free_events.back();
+        S->free_events.pop_back();
+        hip_ok(S, hipEventRecord(S->events[(size_t)r.ev], S->copy_stream));
+        S->dma_pending.push_back(k);
     } else {
+        publish(S, k, r.dev_src);
+    }
+    r.state = kRunning;
+    S->running.push_back(k);
+}
+
+// Writes request k's descriptor to the next slot and announces it (called
+// with mu held).  hsrc: the caller's pixels for the loop to stage, or 0 when
+// they are already in the pool.
+void publish(adct_server* S, int64_t k, uint64_t hsrc) {
+    Req& r = S->reqs[(size_t)k];
+    const Block b = block_of(S, r);
+    {
         ReqDesc d;
         memset(&d, 0, sizeof d);
         d.src = (uint64_t)(uintptr_t)b.src;
-        d.hsrc = r.dev_src;
+        d.hsrc = hsrc;
         d.hsrc_pitch = (uint32_t)r.pitch;
         d.dst = (uint64_t)(uintptr_t)b.dst;
         d.q = (uint64_t)(uintptr_t)b.q;
@@ -549,8 +590,23 @@ void issue(adct_server* S, int64_t k) {
         __atomic_store_n(S->h_count, (uint32_t)(slot + 1), __ATOMIC_RELEASE);
         if (!S->stopping && loop_exited(S)) launch_loop(S);
     }
-    r.state = kRunning;
-    S->running.push_back(k);
+}
+
+// Publishes the requests whose DMA copies are done (called with mu held);
+// the copies run on one stream and finish in issue order.  Returns whether
+// any was published.
+bool publish_copied(adct_server* S) {
+    size_t i = 0;
+    while (i < S->dma_pending.size() && event_done(S, S->reqs[(size_t)S->dma_pending[i]].ev)) {
+        const int64_t k = S->dma_pending[i];
+        Req& r = S->reqs[(size_t)k];
+        S->free_events.push_back(r.ev);
+        r.ev = -1;
+        publish(S, k, 0);
+        ++i;
+    }
+    S->dma_pending.erase(S->dma_pending.begin(), S->dma_pending.begin() + (ptrdiff_t)i);
+    return i > 0;
 }
 
 bool event_done(adct_server* S, int ev) {
@@ -633,11 +689,12 @@ void serve_thread(adct_server* S) {
                 issue(S, i);
                 ++admitted;
             });
+        const bool copied = S->cfg.mode == ADCT_SERVE_PERSISTENT && publish_copied(S);
         if (S->cfg.mode == ADCT_SERVE_PERSISTENT && !S->running.empty() && !S->stopping && loop_exited(S))
             launch_loop(S);  // the loop went idle and exited before this work was published
         const bool fin = poll_done(S);
         if (fin) S->done_cv.notify_all();
-        if (admitted || fin) continue;
+        if (admitted || copied || fin) continue;
         // nothing happened: poll again soon while work is outstanding or about
         // to arrive, otherwise sleep until a submission, a release or the
         // next arrival
@@ -661,6 +718,7 @@ void free_server(adct_server* S) {
     for (hipEvent_t e : S->events)
         if (e) (void)hipEventDestroy(e);
     if (S->stream) (void)hipStreamDestroy(S->stream);
+    if (S->copy_stream) (void)hipStreamDestroy(S->copy_stream);
     if (S->pool_mem) (void)hipFree(S->pool_mem);
     if (S->d_desc) (void)hipFree(S->d_desc);
     if (S->d_state) (void)hipFree(S->d_state);
@@ -685,8 +743,10 @@ int adct_server_create(adct_server** out, const adct_server_cfg* cfg_in) {
     adct_server_cfg cfg = *cfg_in;
     if (cfg.wgs_per_cu == 0) cfg.wgs_per_cu = 2;
     if (cfg.idle_polls == 0) cfg.idle_polls = 100000;
+    if (cfg.dma_min_pixels == 0) cfg.dma_min_pixels = ADCT_SERVE_DMA_MIN_DEFAULT;
     if (cfg.pool_bytes < 1024 || cfg.max_inflight < 1 || cfg.max_requests < 1 || cfg.tiles_per_item < 0 ||
         cfg.tiles_per_item % 16 || cfg.wgs_per_cu < 1 || cfg.wgs_per_cu > 8 || cfg.idle_polls < 1 ||
+        cfg.dma_min_pixels < -1 ||
         (cfg.mode != ADCT_SERVE_PERSISTENT && cfg.mode != ADCT_SERVE_PLAIN))
         return ADCT_E_ARG;
     adct_server* S = new adct_server();
@@ -710,7 +770,9 @@ int adct_server_create(adct_server** out, const adct_server_cfg* cfg_in) {
               hipHostMalloc(reinterpret_cast<void**>(&S->h_comp), n * sizeof(Completion), mapped) == hipSuccess &&
               hipHostMalloc(reinterpret_cast<void**>(&S->h_stop), 128, mapped) == hipSuccess &&
               hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) == hipSuccess;
-    if (cfg.mode == ADCT_SERVE_PLAIN) {
+    const bool use_dma = cfg.mode == ADCT_SERVE_PERSISTENT && cfg.dma_min_pixels > 0;
+    if (ok && use_dma) ok = hipStreamCreateWithFlags(&S->copy_stream, hipStreamNonBlocking) == hipSuccess;
+    if (cfg.mode == ADCT_SERVE_PLAIN || use_dma) {
         S->events.resize((size_t)cfg.max_inflight, nullptr);
         for (int i = 0; ok && i < cfg.max_inflight; ++i) {
             ok = hipEventCreateWithFlags(&S->events[(size_t)i], hipEventDisableTiming) == hipSuccess;

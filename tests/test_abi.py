@@ -40,7 +40,7 @@ def test_binding_covers_every_declared_symbol():
 
 
 def test_abi_version():
-    assert adct.abi_version() == 1
+    assert adct.abi_version() == 2
 
 
 def test_constants_match_oracle():

@@ -31,8 +31,12 @@ def _full_result():
             "uneven_batch_4096": {"tiles": 17660000, "ms": 5.3, "frac_of_8tbs": 0.64,
                                   "quant_qp27": {"ms": 4.05, "frac_of_8tbs": 0.56}},
             "serving_poisson": {"rate": {lam: serve_row for lam in (200, 500, 1000, 2000, 5000)},
-                                "capacity": {m: {"tiles_per_s": 1.0e9, "p99_ms": 1.0} for m in
-                                             ("persistent", "plain")}},
+                                "capacity": {m: {"max_rate_p99_within_bound": 10000, "p99_bound_ms": 1.0,
+                                                 "tiles_per_s": 1.2e8, "burst_tiles_per_s": 2.0e8,
+                                                 "burst_p99_ms": 50.0,
+                                                 "tried": {lam: {"p50_ms": 0.1, "p99_ms": 0.5, "tiles_per_s": 1e8}
+                                                           for lam in bench.CAPACITY_RATES}}
+                                             for m in ("persistent", "plain")}},
             "image_experiment_zigzag_1024x512x512": {"r": {r: {"psnr_db": 30.0} for r in bench.ZIGZAG_R}},
         },
         "detail_file": "gpurun_out/bench_detail.json",

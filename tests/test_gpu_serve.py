@@ -251,3 +251,45 @@ def test_benchmark_configuration_full_size_requests(mode):
     # 46 (the 4096 x 4096 one) against the oracle as well
     _check_all(srv, tickets, [v.numpy() for v in views], oracle_every=23)
     srv.close()
+
+
+@pytest.mark.parametrize("dma_min", [1, 512 * 512, -1])
+def test_dma_copied_requests_match_alone(dma_min):
+    # dma_min_pixels = 1: every request is copied into the pool by the DMA
+    # engine and published afterwards; 512 x 512: a mix of DMA-copied and
+    # loop-staged requests in one stream of arrivals; -1: none is copied
+    imgs, pins = _requests(60, 256, 1024, seed=29_000)
+    arr = synth.poisson_arrivals(3000.0, len(pins), seed=29_001)
+    srv = adct.Server(pool_bytes=1 << 30, qp=QP, max_inflight=64, max_requests=64, dma_min_pixels=dma_min)
+    t0 = adct.now_ns() + 2_000_000
+    tickets = [srv.submit(p, t0 + int(a * 1e9)) for p, a in zip(pins, arr)]
+    srv.wait_all(60)
+    st = srv.stats()
+    assert st["completed"] == 60 and st["cancelled"] == 0
+    _check_all(srv, tickets, imgs, oracle_every=29)
+    srv.close()
+
+
+def test_dma_copied_pitched_request_and_pool_reuse():
+    # a pitched pinned request through the DMA path, then requests that reuse
+    # its pool block (the block's old contents must not be read back)
+    img = synth.ar1_image(29_500, 256, 320)
+    wide = torch.zeros((256, 384), dtype=torch.uint8).pin_memory()
+    wide[:, 16:336] = torch.from_numpy(img)
+    srv = adct.Server(pool_bytes=1 << 20, qp=QP, max_inflight=1, max_requests=8, dma_min_pixels=1)
+    t = srv.submit(wide[:, 16:336])
+    srv.wait_all(30)
+    _check_all(srv, [t], [img], oracle_every=1)
+    imgs, pins = _requests(4, 256, 320, seed=29_600)
+    tickets = [srv.submit(p) for p in pins]
+    for k, tk in enumerate(tickets):
+        while srv.poll(tk)[0] == adct.PENDING:
+            time.sleep(0.001)
+        _check_all(srv, [tk], [imgs[k]])
+    srv.close()
+
+
+def test_server_rejects_bad_dma_threshold():
+    with pytest.raises(adct.AdctError) as e:
+        adct.Server(pool_bytes=1 << 20, qp=QP, max_requests=4, dma_min_pixels=-2)
+    assert e.value.code == adct.E_ARG
