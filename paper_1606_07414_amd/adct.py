@@ -24,7 +24,7 @@ U8, I16 = 1, 2
 class AdctError(RuntimeError):
     def __init__(self, code: int, where: str):
         self.code = code
-        super().__init__(f"{where}: {_lib().adct_strerror(code).decode()} ({code})")
+        super().__init__(f"{where}: {policy_lib().adct_strerror(code).decode()} ({code})")
 
 
 class Plane(ctypes.Structure):
@@ -162,6 +162,30 @@ def _lib():
 def lib():
     """The loaded ctypes library (loads it on first use)."""
     return _lib()
+
+
+# The host policy (status strings, work queue, pool, admission, percentile)
+# is plain C++; ADCT_POLICY_LIB may name a CPU-only build of it (the
+# sanitizer-instrumented one of the tests), which then serves these calls.
+_POLICY_NAMES = ("adct_strerror", "adct_work_queue", "adct_pool_simulate", "adct_admission_simulate",
+                 "adct_percentile")
+_POLICY = None
+
+
+def policy_lib():
+    global _POLICY
+    path = os.environ.get("ADCT_POLICY_LIB")
+    if not path:
+        return _lib()
+    if _POLICY is None:
+        pl = ctypes.CDLL(path)
+        for name in _POLICY_NAMES:
+            res, args = _SIGNATURES[name]
+            fn = getattr(pl, name)
+            fn.restype = res
+            fn.argtypes = args
+        _POLICY = pl
+    return _POLICY
 
 
 def _check(rc: int, where: str) -> int:
@@ -558,10 +582,10 @@ def work_queue(tiles_per_job, tiles_per_group: int, groups_per_item: int) -> np.
     """Items (job, first tile, tile count) as built by the library, shape (n, 3)."""
     t = np.ascontiguousarray(np.asarray(tiles_per_job, dtype=np.int64).reshape(-1))
     n = _I64(0)
-    _check(_lib().adct_work_queue(t.ctypes.data, t.shape[0], tiles_per_group, groups_per_item, None, 0,
+    _check(policy_lib().adct_work_queue(t.ctypes.data, t.shape[0], tiles_per_group, groups_per_item, None, 0,
                                   ctypes.byref(n)), "work_queue")
     items = np.empty((max(n.value, 1), 3), dtype=np.uint32)
-    _check(_lib().adct_work_queue(t.ctypes.data, t.shape[0], tiles_per_group, groups_per_item, items.ctypes.data,
+    _check(policy_lib().adct_work_queue(t.ctypes.data, t.shape[0], tiles_per_group, groups_per_item, items.ctypes.data,
                                   n.value, ctypes.byref(n)), "work_queue")
     return items[:n.value]
 
@@ -718,7 +742,7 @@ def pool_simulate(capacity: int, ops):
     ops = np.ascontiguousarray(np.asarray(ops, dtype=np.int64))
     out = np.empty(ops.shape[0], dtype=np.int64)
     hw = _I64(0)
-    _check(_lib().adct_pool_simulate(capacity, ops.ctypes.data, ops.shape[0], out.ctypes.data, ctypes.byref(hw)),
+    _check(policy_lib().adct_pool_simulate(capacity, ops.ctypes.data, ops.shape[0], out.ctypes.data, ctypes.byref(hw)),
            "pool_simulate")
     return out, hw.value
 
@@ -728,7 +752,7 @@ def admission_simulate(capacity: int, max_inflight: int, arrival, nbytes, hold):
     b = np.ascontiguousarray(np.asarray(nbytes, dtype=np.int64))
     h = np.ascontiguousarray(np.asarray(hold, dtype=np.int64))
     out = np.empty(a.shape[0], dtype=np.int64)
-    _check(_lib().adct_admission_simulate(capacity, max_inflight, a.ctypes.data, b.ctypes.data, h.ctypes.data,
+    _check(policy_lib().adct_admission_simulate(capacity, max_inflight, a.ctypes.data, b.ctypes.data, h.ctypes.data,
                                           a.shape[0], out.ctypes.data), "admission_simulate")
     return out
 
@@ -736,5 +760,5 @@ def admission_simulate(capacity: int, max_inflight: int, arrival, nbytes, hold):
 def percentile(values, p: float) -> float:
     v = np.ascontiguousarray(np.asarray(values, dtype=np.float64))
     out = _D(0.0)
-    _check(_lib().adct_percentile(v.ctypes.data, v.shape[0], p, ctypes.byref(out)), "percentile")
+    _check(policy_lib().adct_percentile(v.ctypes.data, v.shape[0], p, ctypes.byref(out)), "percentile")
     return out.value

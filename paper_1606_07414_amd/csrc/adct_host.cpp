@@ -1,5 +1,6 @@
-// Host-only parts of the C ABI: status strings, constants, quantisation
-// tables and PSNR.  No HIP calls, so all of it runs without a GPU.
+// Host-only parts of the C ABI: constants, quantisation tables, PSNR and the
+// host execution of the butterflies.  No HIP calls, so all of it runs
+// without a GPU.
 #include <math.h>
 #include <stdint.h>
 #include <string.h>
@@ -96,24 +97,6 @@ using namespace adct;
 
 extern "C" {
 
-const char* adct_strerror(int code) {
-    switch (code) {
-        case ADCT_OK: return "ok";
-        case ADCT_PENDING: return "pending";
-        case ADCT_E_ARG: return "invalid argument";
-        case ADCT_E_SHAPE: return "plane sides must be positive multiples of 16 with a valid pitch";
-        case ADCT_E_DTYPE: return "unsupported sample type";
-        case ADCT_E_HIP: return "HIP runtime error";
-        case ADCT_E_NOMEM: return "out of memory";
-        case ADCT_E_TOO_LARGE: return "request larger than the available capacity";
-        case ADCT_E_STOPPED: return "stopped";
-        case ADCT_E_TIMEOUT: return "timed out";
-        case ADCT_E_NOTFOUND: return "not found";
-        case ADCT_E_ALIGN: return "pointer or pitch not 16-byte aligned";
-        default: return "unknown status";
-    }
-}
-
 int adct_abi_version(void) { return ADCT_ABI_VERSION; }
 
 int adct_constants(int32_t* T256, double* s16, int32_t* W256) {
@@ -179,29 +162,6 @@ int adct_default_tune(adct_tune* out) {
     out->wgs_per_cu = 4;
     out->reserved = 0;
     return ADCT_OK;
-}
-
-int adct_work_queue(const int64_t* tiles_per_job, int32_t njobs, int32_t tiles_per_group, int32_t groups_per_item,
-                    uint32_t* items, int64_t capacity, int64_t* n_items) {
-    if (!tiles_per_job || njobs < 0 || !n_items || capacity < 0) return ADCT_E_ARG;
-    if (tiles_per_group <= 0 || groups_per_item <= 0) return ADCT_E_ARG;
-    const int64_t span = (int64_t)tiles_per_group * groups_per_item;
-    int64_t n = 0;
-    for (int32_t j = 0; j < njobs; ++j) {
-        const int64_t t = tiles_per_job[j];
-        if (t < 0 || t > (int64_t)INT32_MAX) return ADCT_E_ARG;
-        for (int64_t first = 0; first < t; first += span) {
-            if (items && n < capacity) {
-                items[3 * n + 0] = (uint32_t)j;
-                items[3 * n + 1] = (uint32_t)first;
-                items[3 * n + 2] = (uint32_t)(t - first < span ? t - first : span);
-            }
-            ++n;
-        }
-    }
-    *n_items = n;
-    if (n > (int64_t)UINT32_MAX) return ADCT_E_TOO_LARGE;
-    return (items && n > capacity) ? ADCT_E_TOO_LARGE : ADCT_OK;
 }
 
 // Host execution of the kernels' 1D butterflies (the same code the GPU

@@ -992,70 +992,4 @@ int adct_server_destroy(adct_server* S) {
     return rc;
 }
 
-// ---- host-policy simulation (no GPU) ------------------------------------------
-
-int adct_pool_simulate(int64_t capacity, const int64_t* ops, int32_t nops, int64_t* out, int64_t* high_water) {
-    if (!ops || !out || nops < 0 || capacity < 0) return ADCT_E_ARG;
-    Pool pool(capacity);
-    std::vector<int64_t> sizes((size_t)nops, 0);
-    for (int32_t i = 0; i < nops; ++i) {
-        if (ops[i] > 0) {
-            out[i] = pool.alloc(ops[i]);
-            if (out[i] >= 0) sizes[(size_t)i] = ops[i];
-        } else {
-            const int64_t j = -ops[i];
-            if (j >= i || sizes[(size_t)j] == 0) return ADCT_E_ARG;
-            pool.release(out[j], sizes[(size_t)j]);
-            sizes[(size_t)j] = 0;
-            out[i] = 0;
-        }
-    }
-    if (high_water) *high_water = pool.high_water();
-    return ADCT_OK;
-}
-
-int adct_admission_simulate(int64_t capacity, int32_t max_inflight, const int64_t* arrival, const int64_t* bytes,
-                            const int64_t* hold, int32_t n, int64_t* admit) {
-    if (!arrival || !bytes || !hold || !admit || n < 0 || max_inflight < 1) return ADCT_E_ARG;
-    Pool pool(capacity);
-    for (int32_t i = 0; i < n; ++i)
-        if (!pool.fits_ever(bytes[i]) || hold[i] < 0) return ADCT_E_TOO_LARGE;
-    std::vector<int64_t> off((size_t)n, -1), end((size_t)n, -1);
-    int64_t head = 0, inflight = 0, now = n ? arrival[0] : 0;
-    while (head < n) {
-        head = admit_in_order(
-            head, n, now, inflight, max_inflight, pool, [&](int64_t i) { return arrival[i]; },
-            [&](int64_t i) { return bytes[i]; }, [](int64_t) { return false; },
-            [&](int64_t i, int64_t o) {
-                admit[i] = now;
-                off[(size_t)i] = o;
-                end[(size_t)i] = now + hold[i];
-            });
-        if (head >= n) break;
-        // next event: the head's arrival or the earliest release
-        int64_t next = arrival[head] > now ? arrival[head] : INT64_MAX;
-        for (int64_t i = 0; i < head; ++i)
-            if (off[(size_t)i] >= 0 && end[(size_t)i] > now) next = std::min(next, end[(size_t)i]);
-        if (next == INT64_MAX) {
-            // all admitted requests are due: release those ending now
-            next = now;
-        }
-        now = next;
-        for (int64_t i = 0; i < head; ++i) {
-            if (off[(size_t)i] >= 0 && end[(size_t)i] <= now) {
-                pool.release(off[(size_t)i], bytes[i]);
-                off[(size_t)i] = -1;
-                --inflight;
-            }
-        }
-    }
-    return ADCT_OK;
-}
-
-int adct_percentile(const double* v, int64_t n, double p, double* out) {
-    if (!v || !out || n < 0 || !(p >= 0.0 && p <= 100.0)) return ADCT_E_ARG;
-    *out = percentile(std::vector<double>(v, v + n), p);
-    return ADCT_OK;
-}
-
 }  // extern "C"

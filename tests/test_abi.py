@@ -246,7 +246,7 @@ def test_work_queue_covers_every_tile_once():
 
 
 def test_work_queue_errors():
-    lib = adct.lib()
+    lib = adct.policy_lib()
     n = ctypes.c_int64(0)
     t = np.array([10, 20], dtype=np.int64)
     assert lib.adct_work_queue(t.ctypes.data, 2, 0, 1, None, 0, ctypes.byref(n)) == adct.E_ARG
