@@ -32,7 +32,11 @@ entries are 8, 16 or 32, so W32 = 1024 / (d_u d_v) is a power of two in
 {1, 2, 4, 8, 16} and reconstructions carry 10 fractional bits:
 clamp(floor((R + 512) / 1024)).  Quantiser tables qs = fp32(s_u s_v / Delta)
 and dqs = fp32(1024 Delta s_u s_v), rounding half away from zero as in the
-16-point oracle.
+16-point oracle.  Levels are the codec's stored type, int16: a level is
+saturated to [-32768, 32767] before it is stored or dequantised.  For
+uint8 samples or residuals within [-255, 255] that never acts (|Y s_u s_v|
+<= 32 * 255 = 8160 and 1 / Delta < 1.6); for int16 samples up to 2047 it
+can, below QP 10.
 
 Parity unpinned for quality figures: the paper prints no PSNR or Table 2
 measures for a 32-point transform.
@@ -168,10 +172,11 @@ def quant_tables_32(qp: int):
 
 
 def quantise_32(coef: np.ndarray, qp: int) -> np.ndarray:
-    """Levels: fp32(Y) * qs in float32, rounded half away from zero."""
+    """Levels: fp32(Y) * qs in float32, rounded half away from zero, then
+    saturated to int16 (the stored type)."""
     qs, _ = quant_tables_32(qp)
     v = np.asarray(coef).astype(np.float32) * qs[None]
-    return O.round_half_away(v.astype(np.float64))
+    return np.clip(O.round_half_away(v.astype(np.float64)), -32768, 32767)
 
 
 def dequantise_32(q: np.ndarray, qp: int) -> np.ndarray:

@@ -137,6 +137,18 @@ def test_quant_tables_closed_form_and_bound():
         assert np.all(np.abs(z - 1024 * q * delta * (s[:, None] * s[None, :])) <= 0.5 + 1e-3 * np.abs(z))
 
 
+def test_level_saturation_acts_only_below_qp10_on_wide_int16():
+    # the largest level magnitude is reached by a constant tile: Y_00 =
+    # 1024 x, B_00 = Y_00 / 32 = 32 x
+    for qp, x, saturates in ((0, 2047, True), (9, 2047, True), (10, 2047, False), (0, 255, False)):
+        tile = np.full((32, 32), x, dtype=np.int16)
+        q = T32.quantise_32(T32.fwd2d_32(tile), qp)
+        exact = O.round_half_away(np.float32(1024 * x) * T32.quant_tables_32(qp)[0][0, 0])
+        assert (q[0, 0, 0] == 32767 and exact > 32767) if saturates else q[0, 0, 0] == exact
+        if not saturates:  # rounding half away from zero is odd-symmetric
+            assert np.array_equal(T32.quantise_32(-T32.fwd2d_32(tile), qp), -q)
+
+
 def test_quant_reconstruction_error_is_bounded():
     rng = np.random.default_rng(11)
     img = rng.integers(-255, 256, (64, 64)).astype(np.int16)
