@@ -356,18 +356,30 @@ __device__ __forceinline__ void zigzag_weights_cols(int p, int r, int32_t (&a)[1
     }
 }
 
+// The quantiser (or dequantiser) factors of columns p and p+8, per log2 d_u
+// - 2.  Taken once, at the start of a group: their per-lane selects may be
+// compiled into indexed loads of the table, and loading them early keeps
+// that latency off the path from the forward transform to the quantiser.
+struct ColFactors {
+    float a[3], b[3];
+};
+
+__device__ __forceinline__ ColFactors col_factors(const Scale5& t, int p) {
+    ColFactors f;
+    column_factors(t, p, f.a);
+    column_factors(t, p + 8, f.b);
+    return f;
+}
+
 // Levels of columns p, p+8, saturated to int16 when SAT (without SAT the
 // caller guarantees that they fit).
 template <bool SAT>
-__device__ __forceinline__ void quant_cols(const Scale5& qs, int p, const int32_t (&a)[16], const int32_t (&b)[16],
+__device__ __forceinline__ void quant_cols(const ColFactors& f, const int32_t (&a)[16], const int32_t (&b)[16],
                                            int32_t (&qa)[16], int32_t (&qb)[16]) {
-    float fa[3], fb[3];
-    column_factors(qs, p, fa);
-    column_factors(qs, p + 8, fb);
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
-        qa[u] = round_away(__fmul_rn((float)a[u], fa[log2_norm(u) - 2]));
-        qb[u] = round_away(__fmul_rn((float)b[u], fb[log2_norm(u) - 2]));
+        qa[u] = round_away(__fmul_rn((float)a[u], f.a[log2_norm(u) - 2]));
+        qb[u] = round_away(__fmul_rn((float)b[u], f.b[log2_norm(u) - 2]));
         if constexpr (SAT) {
             qa[u] = clamp_i32(qa[u], -32768, 32767);
             qb[u] = clamp_i32(qb[u], -32768, 32767);
@@ -375,14 +387,11 @@ __device__ __forceinline__ void quant_cols(const Scale5& qs, int p, const int32_
     }
 }
 
-__device__ __forceinline__ void dequant_cols(const Scale5& dqs, int p, int32_t (&a)[16], int32_t (&b)[16]) {
-    float fa[3], fb[3];
-    column_factors(dqs, p, fa);
-    column_factors(dqs, p + 8, fb);
+__device__ __forceinline__ void dequant_cols(const ColFactors& f, int32_t (&a)[16], int32_t (&b)[16]) {
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
-        a[u] = round_away(__fmul_rn((float)a[u], fa[log2_norm(u) - 2]));
-        b[u] = round_away(__fmul_rn((float)b[u], fb[log2_norm(u) - 2]));
+        a[u] = round_away(__fmul_rn((float)a[u], f.a[log2_norm(u) - 2]));
+        b[u] = round_away(__fmul_rn((float)b[u], f.b[log2_norm(u) - 2]));
     }
 }
 
@@ -493,6 +502,11 @@ __device__ __forceinline__ void process_group(const GroupArgs& a, uint32_t g0, u
     uint32_t xk[16];   // packed input or reference samples (row role), for the SSE
     uint4 ra0, ra1, rb0, rb1;
     int32_t ya[16], yb[16];
+    constexpr bool kQuant = M::MID == kMidQuant || M::MID == kMidQuantFit;
+    constexpr bool kDequant = (kQuant && M::OUT != kOutNothing) || M::MID == kMidDequant;
+    ColFactors qf{}, dqf{};
+    if constexpr (kQuant) qf = col_factors(qs, cp);
+    if constexpr (kDequant) dqf = col_factors(dqs, cp);
 
     // ---------------- input --------------------------------------------------
     if constexpr (M::IN == kInSamples) {
@@ -541,7 +555,7 @@ __device__ __forceinline__ void process_group(const GroupArgs& a, uint32_t g0, u
         // 1.6, so their levels always fit int16
         constexpr bool sat = M::MID == kMidQuant && sizeof(S) == 2;
         int32_t qa[16], qb[16];
-        quant_cols<sat>(qs, cp, ya, yb, qa, qb);
+        quant_cols<sat>(qf, ya, yb, qa, qb);
         if constexpr (M::STORE == kStoreQ) {
             if (a.cout) {
                 __syncthreads();
@@ -556,10 +570,10 @@ __device__ __forceinline__ void process_group(const GroupArgs& a, uint32_t g0, u
                 ya[u] = qa[u];
                 yb[u] = qb[u];
             }
-            dequant_cols(dqs, cp, ya, yb);
+            dequant_cols(dqf, ya, yb);
         }
     } else if constexpr (M::MID == kMidDequant) {
-        dequant_cols(dqs, cp, ya, yb);
+        dequant_cols(dqf, ya, yb);
     } else if constexpr (M::MID == kMidZonal) {
         zonal_weights_cols<M::ZR, M::XF>(cp, a.r, ya, yb);
     } else if constexpr (M::MID == kMidZigzag) {
