@@ -317,6 +317,55 @@ int adct_t8_encode_zonal(const adct_plane* src, int r, int32_t* coef, const adct
 int adct_t8_encode_quant(const adct_plane* src, int qp, int16_t* q, const adct_plane* dst,
                          int32_t image_height, int64_t* sse, void* stream);
 
+/* ---- the 32-point extension on 32x32 blocks ------------------------- */
+/* Section 5 names 32- and 64-point extensions of the approach by the
+ * scaled construction of its reference [Jridi2015] and prints no matrix;
+ * these calls take the construction by which Section 2.1 builds T from two
+ * 8-point blocks one level up:  T32 = P32 diag(T, T) B32, where B32 folds a
+ * row into the sums x_j + x_{31-j} and differences x_j - x_{31-j}, T
+ * (Section 2.1, 44 additions by Section 2.2) transforms each half, and P32
+ * interleaves them (coefficient 2k from the sums, 2k + 1 from the
+ * differences): 120 additions, entries in {0, +1, -1}, and T32 T32^T =
+ * diag(2 d[u / 2]) with d the diagonal of T T^T.  The 32x32 codec mirrors
+ * the 16-point one: S32 = diag(T32 T32^T)^(-1/2) folded into the zonal
+ * weights W32 = 1024 / (d_u d_v) or the quantiser tables qs = fp32(s_u s_v
+ * / Delta), dqs = fp32(1024 Delta s_u s_v); levels rounded half away from
+ * zero and saturated to int16; reconstruction clamp(floor((R + 512) /
+ * 1024)).  Planes: sides multiples of 32 (else ADCT_E_SHAPE), sample (0,0)
+ * and the pitch 16-byte aligned (else ADCT_E_ALIGN); coefficient arrays are
+ * block-major [nblk32][32][32], block k = by * (width/32) + bx, element
+ * u*32 + v, 16-byte aligned; image_height a multiple of 32. */
+
+/* Host copies of T32 (row-major), the diagonal of S32 and W32. */
+int adct_t32_constants(int32_t* T1024, double* s32, int32_t* W1024);
+
+/* Host copies of the 32x32 quantisation tables for `qp` in [0, 63]. */
+int adct_t32_quant_tables(int qp, float* qs1024, float* dqs1024);
+
+/* The kernels' 32-point butterflies run on the host with every addition
+ * and subtraction counted (which = 0: T32, 1: T32^T); 32 values in and out. */
+int adct_t32_host_butterfly_count(int32_t which, const int32_t* in32, int32_t* out32, int64_t* additions);
+
+/* Y = T32 A T32^T for every 32x32 block A of src (U8 or I16); coef: device
+ * int32 [nblk32][32][32]. */
+int adct_t32_fwd2d(const adct_plane* src, int32_t* coef, void* stream);
+
+/* T32^T Y T32 for every block (block-major int32 in and out). */
+int adct_t32_inv2d(const int32_t* coef, int64_t nblk, int32_t* out, void* stream);
+
+/* Single-pass 32x32 encoder with reconstruction, zonal form: Y stored to
+ * coef unless NULL, the top-left r x r coefficients kept with S32 folded in
+ * (r in [0, 32]), inverse, rounding and clamping into dst ([0, 255] for U8,
+ * [-255, 255] for I16), and the exact per-image SSE when sse is non-NULL. */
+int adct_t32_encode_zonal(const adct_plane* src, int r, int32_t* coef, const adct_plane* dst,
+                          int32_t image_height, int64_t* sse, void* stream);
+
+/* Single-pass 32x32 encoder, quantised form: levels stored unless NULL,
+ * dequantisation to 10 fractional bits, inverse, rounding, clamping and the
+ * optional SSE. */
+int adct_t32_encode_quant(const adct_plane* src, int qp, int16_t* q, const adct_plane* dst,
+                          int32_t image_height, int64_t* sse, void* stream);
+
 /* ---- mixed 8/16-point coding ------------------------------------------ */
 /* The codec of the second video scenario of Section 3.2, in which both the
  * 8-point (T8) and the 16-point (T) transforms are the approximations.  The

@@ -110,6 +110,13 @@ _SIGNATURES = {
     "adct_t8_encode_zonal": (ctypes.c_int, [_PP, ctypes.c_int, _P, _PP, _I32, _P, _P]),
     "adct_t8_encode_quant": (ctypes.c_int, [_PP, ctypes.c_int, _P, _PP, _I32, _P, _P]),
     "adct_mixed_encode": (ctypes.c_int, [_PP, ctypes.c_int, _I64, _P, _P, _PP, _I32, _P, _P]),
+    "adct_t32_constants": (ctypes.c_int, [_P, _P, _P]),
+    "adct_t32_quant_tables": (ctypes.c_int, [ctypes.c_int, _P, _P]),
+    "adct_t32_host_butterfly_count": (ctypes.c_int, [_I32, _P, _P, ctypes.POINTER(_I64)]),
+    "adct_t32_fwd2d": (ctypes.c_int, [_PP, _P, _P]),
+    "adct_t32_inv2d": (ctypes.c_int, [_P, _I64, _P, _P]),
+    "adct_t32_encode_zonal": (ctypes.c_int, [_PP, ctypes.c_int, _P, _PP, _I32, _P, _P]),
+    "adct_t32_encode_quant": (ctypes.c_int, [_PP, ctypes.c_int, _P, _PP, _I32, _P, _P]),
     "adct_check": (ctypes.c_int, [_P]),
     "adct_recon": (ctypes.c_int, [_P, _PP, _P]),
     "adct_sse": (ctypes.c_int, [_PP, _PP, _I32, _P, _P]),
@@ -500,6 +507,70 @@ def t8_encode_quant(src, qp: int, dst, q=None, image_height=None, sse=None, want
     ih, sse, sp = _sse_out(src, image_height, sse, want_sse)
     _check(_lib().adct_t8_encode_quant(ctypes.byref(ps), qp, q.data_ptr() if q is not None else None,
                                        ctypes.byref(pd), ih, sp, _stream(stream)), "t8_encode_quant")
+    return sse
+
+
+def t32_constants():
+    """(T32 int32 32x32, s32 float64 [32], W32 int32 32x32)."""
+    T = np.empty(1024, np.int32)
+    s = np.empty(32, np.float64)
+    W = np.empty(1024, np.int32)
+    _check(_lib().adct_t32_constants(T.ctypes.data, s.ctypes.data, W.ctypes.data), "t32_constants")
+    return T.reshape(32, 32), s, W.reshape(32, 32)
+
+
+def t32_quant_tables(qp: int):
+    qs = np.empty(1024, np.float32)
+    dqs = np.empty(1024, np.float32)
+    _check(_lib().adct_t32_quant_tables(qp, qs.ctypes.data, dqs.ctypes.data), "t32_quant_tables")
+    return qs.reshape(32, 32), dqs.reshape(32, 32)
+
+
+def t32_host_butterfly_count(x, inverse: bool = False):
+    """(output, additions) of the kernels' 32-point butterfly run on the host."""
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.int32).reshape(32))
+    y = np.empty(32, np.int32)
+    n = _I64(0)
+    _check(_lib().adct_t32_host_butterfly_count(1 if inverse else 0, x.ctypes.data, y.ctypes.data, ctypes.byref(n)),
+           "t32_host_butterfly_count")
+    return y, n.value
+
+
+def _nblk32(src):
+    return (src.shape[0] // 32) * (src.shape[1] // 32)
+
+
+def t32_fwd2d(src, coef=None, stream=None):
+    torch = _torch()
+    if coef is None:
+        coef = torch.empty((_nblk32(src), 32, 32), dtype=torch.int32, device=src.device)
+    p = plane(src)
+    _check(_lib().adct_t32_fwd2d(ctypes.byref(p), coef.data_ptr(), _stream(stream)), "t32_fwd2d")
+    return coef
+
+
+def t32_inv2d(coef, out=None, stream=None):
+    torch = _torch()
+    n = coef.numel() // 1024
+    if out is None:
+        out = torch.empty_like(coef)
+    _check(_lib().adct_t32_inv2d(coef.data_ptr(), n, out.data_ptr(), _stream(stream)), "t32_inv2d")
+    return out
+
+
+def t32_encode_zonal(src, r: int, dst, coef=None, image_height=None, sse=None, want_sse=True, stream=None):
+    ps, pd = plane(src), plane(dst)
+    ih, sse, sp = _sse_out(src, image_height, sse, want_sse)
+    _check(_lib().adct_t32_encode_zonal(ctypes.byref(ps), r, coef.data_ptr() if coef is not None else None,
+                                        ctypes.byref(pd), ih, sp, _stream(stream)), "t32_encode_zonal")
+    return sse
+
+
+def t32_encode_quant(src, qp: int, dst, q=None, image_height=None, sse=None, want_sse=True, stream=None):
+    ps, pd = plane(src), plane(dst)
+    ih, sse, sp = _sse_out(src, image_height, sse, want_sse)
+    _check(_lib().adct_t32_encode_quant(ctypes.byref(ps), qp, q.data_ptr() if q is not None else None,
+                                        ctypes.byref(pd), ih, sp, _stream(stream)), "t32_encode_quant")
     return sse
 
 

@@ -8,6 +8,7 @@
 #include "adct.h"
 #include "adct_internal.hpp"
 #include "adct_t8_common.hpp"
+#include "adct_t32_common.hpp"
 #include "adct_round.hpp"
 
 namespace adct {
@@ -190,6 +191,53 @@ int adct_host_butterfly_count(int32_t which, const int32_t* in16, int32_t* out16
     for (int i = 0; i < 16; ++i) {
         if (y[i].v < INT32_MIN || y[i].v > INT32_MAX) return ADCT_E_ARG;
         out16[i] = (int32_t)y[i].v;
+    }
+    *additions = CountedInt::ops;
+    return ADCT_OK;
+}
+
+int adct_t32_constants(int32_t* T1024, double* s32, int32_t* W1024) {
+    // T32 = P32 diag(T, T) B32: row 2k is row k of T on the folded sums
+    // (T32[2k][j] = T32[2k][31-j] = T[k][j]), row 2k+1 row k of T on the
+    // folded differences (T32[2k+1][j] = -T32[2k+1][31-j] = T[k][j])
+    for (int u = 0; u < 32; ++u) {
+        const int k = u >> 1, odd = u & 1;
+        if (T1024)
+            for (int j = 0; j < 16; ++j) {
+                T1024[u * 32 + j] = kT[k][j];
+                T1024[u * 32 + 31 - j] = odd ? -kT[k][j] : kT[k][j];
+            }
+        if (s32) s32[u] = 1.0 / sqrt((double)(1 << l32(u)));
+        if (W1024)
+            for (int v = 0; v < 32; ++v) W1024[u * 32 + v] = 1024 >> (l32(u) + l32(v));
+    }
+    return ADCT_OK;
+}
+
+int adct_t32_quant_tables(int qp, float* qs1024, float* dqs1024) {
+    float qs[5], dqs[5];
+    if (!quant_scales32(qp, qs, dqs)) return ADCT_E_ARG;
+    for (int u = 0; u < 32; ++u)
+        for (int v = 0; v < 32; ++v) {
+            const int c = l32(u) + l32(v) - 6;
+            if (qs1024) qs1024[u * 32 + v] = qs[c];
+            if (dqs1024) dqs1024[u * 32 + v] = dqs[c];
+        }
+    return ADCT_OK;
+}
+
+int adct_t32_host_butterfly_count(int32_t which, const int32_t* in32, int32_t* out32, int64_t* additions) {
+    if (!in32 || !out32 || !additions || which < 0 || which > 1) return ADCT_E_ARG;
+    CountedInt x[32], y[32];
+    CountedInt::ops = 0;
+    for (int i = 0; i < 32; ++i) x[i].v = in32[i];
+    if (which == 0)
+        fwd32(x, y);
+    else
+        inv32(x, y);
+    for (int i = 0; i < 32; ++i) {
+        if (y[i].v < INT32_MIN || y[i].v > INT32_MAX) return ADCT_E_ARG;
+        out32[i] = (int32_t)y[i].v;
     }
     *additions = CountedInt::ops;
     return ADCT_OK;

@@ -1,0 +1,404 @@
+// The 32x32 codec of the 32-point extension T32 (butterflies in
+// adct_t32_common.hpp): forward transform, zonal retention or quantisation
+// with S folded in, inverse, rounding and the per-image SSE, one pass.
+//
+// A workgroup of 256 threads codes 8 consecutive tiles (raster order).
+//   row role     rt = tid % 8, rr = tid / 8: row rr of tile rt, so the 8
+//                lanes of one sample row read 8 horizontally adjacent
+//                32-sample segments (contiguous for tiles of one tile row)
+//   column role  ct = tid / 32, cv = tid % 32: column cv of tile ct, so the
+//                32 lanes of a half-wave touch 32 adjacent coefficients of
+//                one row of a block (one contiguous 128-byte run for int32)
+// The row pass runs in registers and goes to LDS ([tile][row][33 words],
+// tile stride 1060 words: both roles' accesses are free of bank
+// conflicts); the column pass, the coefficient domain and the inverse
+// column pass run in the column role; the inverse row pass in the row role
+// again after a second LDS transpose.  Coefficients and levels are stored
+// straight from the column role: for each frequency u, a half-wave writes
+// one contiguous row of a block.
+//
+// Fixed point: the weights 1024 / (d_u d_v) make T32^T (W . T32 X T32^T) T32
+// = 1024 X exact; reconstructions are rounded as floor((R + 512) / 1024).
+#include <hip/hip_runtime.h>
+
+#include "adct_core.hpp"
+#include "adct_internal.hpp"
+#include "adct_round.hpp"
+#include "adct_t32_common.hpp"
+#include "adct_tile.hpp"
+
+namespace adct {
+namespace {
+
+enum Op32 { kFwd32 = 0, kZonal32 = 1, kQuant32 = 2 };
+
+struct Args32 {
+    const char* src;
+    int64_t src_pitch;
+    char* dst;
+    int64_t dst_pitch;
+    void* cout;              // int32 Y (forward, zonal) or int16 levels (quant); null: not stored
+    uint32_t nblk, bw;       // tiles, tiles per tile row
+    FastDiv bwdiv, ipbdiv;   // / bw, / tile rows per image
+    int32_t r;               // zonal size
+    Scale5 qs, dqs;          // per class c = log2 d_u + log2 d_v - 6
+    unsigned long long* sse; // per image, or null
+    uint32_t spread_rows;    // 0: workgroup b takes group b; else interleaved (see k_t32)
+};
+
+constexpr int kTiles32 = 8;                // tiles per workgroup
+constexpr int kRow32 = 33;                 // LDS words per staged row
+constexpr int kTile32 = 32 * kRow32 + 4;   // LDS words per staged tile
+// Workgroups of a launch that adds to the SSE of large images are dealt
+// over the plane in this many interleaved streams (as the 16-point group
+// kernel does), so that the workgroups resident at one time add to many
+// images' sums instead of queueing on the atomics of a few.
+constexpr uint32_t kSpread32 = 256;
+constexpr uint32_t kSpreadMin32 = 64;      // groups of 8 tiles per image
+
+// Raw words of one 32-sample row (uint8: 8 words, int16: 16) and their
+// samples as int32.
+template <typename S>
+struct Row32 {
+    static constexpr int kWords = 8 * (int)sizeof(S);
+    uint32_t w[kWords];
+};
+
+template <typename S>
+__device__ __forceinline__ void load_row32(const char* p, Row32<S>& r) {
+#pragma unroll
+    for (int k = 0; k < Row32<S>::kWords / 4; ++k) {
+        const uint4 v = reinterpret_cast<const uint4*>(p)[k];
+        r.w[4 * k] = v.x;
+        r.w[4 * k + 1] = v.y;
+        r.w[4 * k + 2] = v.z;
+        r.w[4 * k + 3] = v.w;
+    }
+}
+
+template <typename S>
+__device__ __forceinline__ int32_t sample32(const Row32<S>& r, int j) {
+    if constexpr (sizeof(S) == 1)
+        return (int32_t)((r.w[j >> 2] >> (8 * (j & 3))) & 0xffu);
+    else
+        return (j & 1) ? ((int32_t)r.w[j >> 1] >> 16) : (int32_t)(int16_t)(r.w[j >> 1] & 0xffffu);
+}
+
+template <typename S>
+__device__ __forceinline__ void store_row32(char* p, const int32_t (&o)[32]) {
+    if constexpr (sizeof(S) == 1) {
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            uint32_t w[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int j = 16 * k + 4 * i;
+                w[i] = (uint32_t)o[j] | ((uint32_t)o[j + 1] << 8) | ((uint32_t)o[j + 2] << 16) |
+                       ((uint32_t)o[j + 3] << 24);
+            }
+            store16(p + 16 * k, make_uint4(w[0], w[1], w[2], w[3]));
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            uint32_t w[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int j = 8 * k + 2 * i;
+                w[i] = ((uint32_t)o[j] & 0xffffu) | ((uint32_t)o[j + 1] << 16);
+            }
+            store16(p + 16 * k, make_uint4(w[0], w[1], w[2], w[3]));
+        }
+    }
+}
+
+// Factors of column v per log2 d_u - 3 (three classes per column).
+__device__ __forceinline__ void column_factors32(const Scale5& t, int v, float (&out)[3]) {
+    const int lv = l32(v);
+#pragma unroll
+    for (int l = 3; l <= 5; ++l) out[l - 3] = pick5(t, l + lv - 6);
+}
+
+template <typename S, int OP, bool STORE, bool SSE>
+__global__ __launch_bounds__(256) void k_t32(Args32 a) {
+    __shared__ int32_t lds[kTiles32 * kTile32];
+    __shared__ long long red[4];
+    const int tid = threadIdx.x;
+    const uint32_t group =
+        a.spread_rows ? (blockIdx.x % kSpread32) * a.spread_rows + blockIdx.x / kSpread32 : blockIdx.x;
+    const uint32_t g0 = group * (uint32_t)kTiles32;
+    if (g0 >= a.nblk) return;  // past the last group (interleaved grids only)
+    const uint32_t ntile = min((uint32_t)kTiles32, a.nblk - g0);
+
+    // ---- row role: load, forward row pass --------------------------------
+    const int rt = tid & 7, rr = tid >> 3;
+    const bool rok = (uint32_t)rt < ntile;
+    const uint32_t rg = g0 + (uint32_t)(rok ? rt : 0);  // lanes past the plane load a valid tile, unused
+    const uint32_t by = fdiv(rg, a.bwdiv), bx = rg - by * a.bw;
+    Row32<S> raw;
+    load_row32<S>(a.src + (int64_t)(by * 32u + (uint32_t)rr) * a.src_pitch + (int64_t)bx * 32 * (int64_t)sizeof(S),
+                  raw);
+    {
+        int32_t x[32], y[32];
+#pragma unroll
+        for (int j = 0; j < 32; ++j) x[j] = sample32<S>(raw, j);
+        fwd32(x, y);
+        int32_t* l = lds + rt * kTile32 + rr * kRow32;
+#pragma unroll
+        for (int v = 0; v < 32; ++v) l[v] = y[v];
+    }
+    __syncthreads();
+
+    // ---- column role: forward column pass, coefficient domain -------------
+    const int ct = tid >> 5, cv = tid & 31;
+    const bool cok = (uint32_t)ct < ntile;
+    const uint32_t cg = g0 + (uint32_t)ct;
+    int32_t Y[32];
+    {
+        int32_t c[32];
+        const int32_t* l = lds + ct * kTile32 + cv;
+#pragma unroll
+        for (int i = 0; i < 32; ++i) c[i] = l[i * kRow32];
+        fwd32(c, Y);  // Y[u] = coefficient (u, cv)
+    }
+    if constexpr (STORE && OP != kQuant32) {
+        if (cok) {
+            int32_t* o = static_cast<int32_t*>(a.cout) + (int64_t)cg * 1024 + cv;
+#pragma unroll
+            for (int u = 0; u < 32; ++u) o[u * 32] = Y[u];
+        }
+    }
+    if constexpr (OP == kFwd32) return;
+    if constexpr (OP == kZonal32) {
+        const bool kv = cv < a.r;
+        const int lv = l32(cv);
+#pragma unroll
+        for (int u = 0; u < 32; ++u) Y[u] = (kv && u < a.r) ? (int32_t)((uint32_t)Y[u] << (10 - l32(u) - lv)) : 0;
+    } else {
+        float fq[3], fd[3];
+        column_factors32(a.qs, cv, fq);
+        column_factors32(a.dqs, cv, fd);
+        int16_t* o = static_cast<int16_t*>(a.cout) + (int64_t)cg * 1024 + cv;
+#pragma unroll
+        for (int u = 0; u < 32; ++u) {
+            const int32_t q = clamp_i32(round_away(__fmul_rn((float)Y[u], fq[l32(u) - 3])), -32768, 32767);
+            if constexpr (STORE) {
+                if (cok) o[u * 32] = (int16_t)q;
+            }
+            Y[u] = round_away(__fmul_rn((float)q, fd[l32(u) - 3]));
+        }
+    }
+    if (cv == 0) Y[0] += 512;  // rounding offset: the DC term reaches every sample with weight 1
+
+    // ---- inverse column pass, transpose, inverse row pass -----------------
+    {
+        int32_t z[32];
+        inv32(Y, z);
+        __syncthreads();  // every forward column read of LDS is done
+        int32_t* l = lds + ct * kTile32 + cv;
+#pragma unroll
+        for (int i = 0; i < 32; ++i) l[i * kRow32] = z[i];
+    }
+    __syncthreads();
+    int32_t R[32];
+    {
+        int32_t c[32];
+        const int32_t* l = lds + rt * kTile32 + rr * kRow32;
+#pragma unroll
+        for (int j = 0; j < 32; ++j) c[j] = l[j];
+        inv32(c, R);
+    }
+    constexpr int32_t lo = sizeof(S) == 1 ? 0 : -255, hi = 255;
+#pragma unroll
+    for (int j = 0; j < 32; ++j) R[j] = clamp_i32(R[j] >> 10, lo, hi);
+    if (rok)
+        store_row32<S>(a.dst + (int64_t)(by * 32u + (uint32_t)rr) * a.dst_pitch + (int64_t)bx * 32 * (int64_t)sizeof(S),
+                       R);
+    if constexpr (SSE) {
+        int32_t s = 0;
+        if (rok) {
+#pragma unroll
+            for (int j = 0; j < 32; ++j) {
+                const int32_t e = R[j] - sample32<S>(raw, j);
+                s += e * e;
+            }
+        }
+        // one atomic per workgroup when its tiles lie in one image, else
+        // one per thread
+        const uint32_t last = g0 + ntile - 1u;
+        const uint32_t img0 = fdiv(fdiv(g0, a.bwdiv), a.ipbdiv);
+        const uint32_t img1 = fdiv(fdiv(last, a.bwdiv), a.ipbdiv);
+        if (img0 == img1) {
+            const long long v = wave_sum64((long long)s);
+            if ((tid & 63) == 0) red[tid >> 6] = v;
+            __syncthreads();
+            if (tid == 0) {
+                const long long t = red[0] + red[1] + red[2] + red[3];
+                if (t) atomicAdd(a.sse + img0, (unsigned long long)t);
+            }
+        } else if (rok && s) {
+            atomicAdd(a.sse + fdiv(by, a.ipbdiv), (unsigned long long)s);
+        }
+    }
+}
+
+// T32^T Y T32 per block (block-major int32 in and out).
+__global__ __launch_bounds__(256) void k_t32_inv(const int32_t* __restrict__ in, int32_t* __restrict__ out,
+                                                uint32_t nblk) {
+    __shared__ int32_t lds[kTiles32 * kTile32];
+    const int tid = threadIdx.x;
+    const uint32_t g0 = blockIdx.x * (uint32_t)kTiles32;
+    const uint32_t ntile = min((uint32_t)kTiles32, nblk - g0);
+    const int ct = tid >> 5, cv = tid & 31;
+    {
+        int32_t Y[32], z[32];
+        const uint32_t cg = g0 + (uint32_t)((uint32_t)ct < ntile ? ct : 0);
+        const int32_t* p = in + (int64_t)cg * 1024 + cv;
+#pragma unroll
+        for (int u = 0; u < 32; ++u) Y[u] = p[u * 32];
+        inv32(Y, z);
+        int32_t* l = lds + ct * kTile32 + cv;
+#pragma unroll
+        for (int i = 0; i < 32; ++i) l[i * kRow32] = z[i];
+    }
+    __syncthreads();
+    const int rt = tid & 7, rr = tid >> 3;
+    if ((uint32_t)rt >= ntile) return;
+    int32_t c[32], R[32];
+    const int32_t* l = lds + rt * kTile32 + rr * kRow32;
+#pragma unroll
+    for (int j = 0; j < 32; ++j) c[j] = l[j];
+    inv32(c, R);
+    int4* q = reinterpret_cast<int4*>(out + (int64_t)(g0 + (uint32_t)rt) * 1024 + rr * 32);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) q[k] = make_int4(R[4 * k], R[4 * k + 1], R[4 * k + 2], R[4 * k + 3]);
+}
+
+__global__ __launch_bounds__(256) void k_t32_zero(unsigned long long* p, uint32_t n) {
+    const uint32_t t = blockIdx.x * 256u + threadIdx.x;
+    if (t < n) p[t] = 0ull;
+}
+
+int launched() { return hipGetLastError() == hipSuccess ? ADCT_OK : ADCT_E_HIP; }
+
+// Planes of the 32-point calls: sides multiples of 32; 16-byte aligned rows.
+int check_plane32(const adct_plane* p) {
+    int rc = check_plane(p);
+    if (rc) return rc;
+    if ((p->height & 31) || (p->width & 31)) return ADCT_E_SHAPE;
+    return ADCT_OK;
+}
+
+int64_t blocks32(const adct_plane* p) { return (int64_t)(p->height / 32) * (p->width / 32); }
+
+template <typename S, int OP, bool STORE>
+void launch32(const Args32& a, hipStream_t s) {
+    const dim3 grid(a.spread_rows ? a.spread_rows * kSpread32 : (a.nblk + kTiles32 - 1) / kTiles32);
+    if (a.sse)
+        hipLaunchKernelGGL((k_t32<S, OP, STORE, true>), grid, dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_t32<S, OP, STORE, false>), grid, dim3(256), 0, s, a);
+}
+
+template <int OP>
+int launch32_typed(int32_t dtype, const Args32& a, hipStream_t s) {
+    if (a.nblk == 0) return ADCT_OK;
+    if (dtype == ADCT_U8) {
+        if (a.cout) launch32<uint8_t, OP, true>(a, s); else launch32<uint8_t, OP, false>(a, s);
+    } else {
+        if (a.cout) launch32<int16_t, OP, true>(a, s); else launch32<int16_t, OP, false>(a, s);
+    }
+    return launched();
+}
+
+// Shared checks and set-up of the encoders (and the forward call, with no
+// destination).
+int setup32(const adct_plane* src, void* coef, const adct_plane* dst, int32_t image_height, int64_t* sse,
+            hipStream_t s, Args32& a) {
+    int rc = check_plane32(src);
+    if (rc) return rc;
+    if (dst) {
+        if ((rc = check_plane32(dst))) return rc;
+        if (!same_shape(src, dst)) return ADCT_E_SHAPE;
+    }
+    if (sse && (image_height <= 0 || (image_height & 31) || src->height % image_height)) return ADCT_E_SHAPE;
+    if (sse && ((uintptr_t)sse & 7)) return ADCT_E_ALIGN;
+    if (coef && (((uintptr_t)coef) & 15)) return ADCT_E_ALIGN;
+    a.src = static_cast<const char*>(src->data);
+    a.src_pitch = src->pitch_bytes;
+    if (dst) {
+        a.dst = static_cast<char*>(dst->data);
+        a.dst_pitch = dst->pitch_bytes;
+    }
+    a.cout = coef;
+    a.nblk = (uint32_t)blocks32(src);
+    a.bw = (uint32_t)(src->width / 32);
+    a.bwdiv = make_fastdiv(a.bw);
+    a.ipbdiv = make_fastdiv(sse ? (uint32_t)(image_height / 32) : 1u);
+    a.sse = reinterpret_cast<unsigned long long*>(sse);
+    if (sse) {
+        const uint32_t groups = (a.nblk + kTiles32 - 1) / kTiles32;
+        const uint32_t image_tiles = (uint32_t)(image_height / 32) * a.bw;
+        if (image_tiles / kTiles32 > kSpreadMin32) a.spread_rows = (groups + kSpread32 - 1) / kSpread32;
+        const uint32_t nimg = (uint32_t)(src->height / image_height);
+        hipLaunchKernelGGL(k_t32_zero, dim3((nimg + 255) / 256), dim3(256), 0, s, a.sse, nimg);
+        return launched();
+    }
+    return ADCT_OK;
+}
+
+}  // namespace
+}  // namespace adct
+
+using namespace adct;
+
+extern "C" {
+
+int adct_t32_fwd2d(const adct_plane* src, int32_t* coef, void* stream) {
+    if (!coef) return ADCT_E_ARG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Args32 a{};
+    int rc = setup32(src, coef, nullptr, 0, nullptr, s, a);
+    if (rc) return rc;
+    return launch32_typed<kFwd32>(src->dtype, a, s);
+}
+
+int adct_t32_inv2d(const int32_t* coef, int64_t nblk, int32_t* out, void* stream) {
+    if (nblk < 0 || nblk > (int64_t)INT32_MAX - kTiles32) return ADCT_E_ARG;
+    if (nblk == 0) return ADCT_OK;  // an empty array may be a null pointer
+    if (!coef || !out) return ADCT_E_ARG;
+    if ((((uintptr_t)coef) & 15) || (((uintptr_t)out) & 15)) return ADCT_E_ALIGN;
+    hipLaunchKernelGGL(k_t32_inv, dim3((unsigned)((nblk + kTiles32 - 1) / kTiles32)), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), coef, out, (uint32_t)nblk);
+    return launched();
+}
+
+int adct_t32_encode_zonal(const adct_plane* src, int r, int32_t* coef, const adct_plane* dst, int32_t image_height,
+                          int64_t* sse, void* stream) {
+    if (r < 0 || r > 32) return ADCT_E_ARG;
+    if (!dst) return ADCT_E_ARG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Args32 a{};
+    int rc = setup32(src, coef, dst, image_height, sse, s, a);
+    if (rc) return rc;
+    a.r = r;
+    return launch32_typed<kZonal32>(src->dtype, a, s);
+}
+
+int adct_t32_encode_quant(const adct_plane* src, int qp, int16_t* q, const adct_plane* dst, int32_t image_height,
+                          int64_t* sse, void* stream) {
+    float qs[5], dqs[5];
+    if (!quant_scales32(qp, qs, dqs)) return ADCT_E_ARG;
+    if (!dst) return ADCT_E_ARG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Args32 a{};
+    int rc = setup32(src, q, dst, image_height, sse, s, a);
+    if (rc) return rc;
+    for (int c = 0; c < 5; ++c) {
+        a.qs.f[c] = qs[c];
+        a.dqs.f[c] = dqs[c];
+    }
+    return launch32_typed<kQuant32>(src->dtype, a, s);
+}
+
+}  // extern "C"

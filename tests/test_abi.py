@@ -425,3 +425,28 @@ def test_noalloc_scratch_size_matches_header():
         m = re.search(r"#define ADCT_NOALLOC_SCRATCH_BYTES \((\d+)u << (\d+)\)", f.read())
     assert m, "ADCT_NOALLOC_SCRATCH_BYTES not found"
     assert adct.NOALLOC_SCRATCH_BYTES == int(m.group(1)) << int(m.group(2))
+
+
+def test_t32_constants_and_tables_match_oracle():
+    from oracle import t32 as T32
+    T, s, W = adct.t32_constants()
+    assert np.array_equal(T, T32.transform_matrix_32())
+    assert np.array_equal(s, T32.scaling_vector_32())
+    assert np.array_equal(W, T32.zonal_weights_32())
+    for qp in (0, 4, 22, 27, 37, 51, 63):
+        qs, dqs = adct.t32_quant_tables(qp)
+        oqs, odqs = T32.quant_tables_32(qp)
+        assert np.array_equal(qs.view(np.uint32), oqs.view(np.uint32)), qp
+        assert np.array_equal(dqs.view(np.uint32), odqs.view(np.uint32)), qp
+
+
+def test_t32_kernel_butterflies_count_120_and_match_oracle():
+    from oracle import t32 as T32
+    A = T32.transform_matrix_32()
+    rng = np.random.default_rng(32)
+    vecs = list(np.eye(32, dtype=np.int64)) + [rng.integers(-65280, 65281, 32) for _ in range(100)]
+    for v in vecs:
+        y, n = adct.t32_host_butterfly_count(v)
+        assert n == 120 and np.array_equal(y, A @ v)
+        x, n = adct.t32_host_butterfly_count(v, inverse=True)
+        assert n == 120 and np.array_equal(x, A.T @ v)
