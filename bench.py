@@ -53,6 +53,9 @@ ENC_SOURCES = ("adct_butterfly.hpp", "adct_tile.hpp", "adct_core.hpp", "adct_pla
 SERVE_TILES_PER_ITEM = 0     # persistent server: tiles per work item (0: chosen per request)
 SERVE_WGS_PER_CU = 2         # persistent server: loop workgroups per CU
 SERVE_DMA_MIN = 0            # persistent server: DMA copy from this many pixels (0: the library default)
+SERVE_TUNE_REQUESTS = 600    # requests replayed per candidate of the loop-shape search
+SERVE_TUNE_TILES_PER_ITEM = (0, 32, 64, 128)   # 0: chosen per request
+SERVE_TUNE_WGS_PER_CU = (1, 2, 4)
 CAPACITY_RATES = (5000, 7500, 10000, 15000, 20000)   # req/s, for the capacity search
 CAPACITY_P99_MS = 1.0
 
@@ -265,8 +268,45 @@ def video(torch, adct, stream, frames=64):
                                   "split_fraction_y_u_v": [k / sp.numel() for sp, k in zip(splits, nsplit)],
                                   "decoder_additions_per_sample": adds / (256 * tiles),
                                   "psnr_yuv_6_1_1_db": float(np.mean((6 * psnrm[0] + psnrm[1] + psnrm[2]) / 8))}
-    res["additions_per_sample_2d"] = {"t16": 2 * 44 / 16, "t8": 2 * 14 / 8}
+    # the same frames with the 32-point extension on 32x32 blocks (every
+    # plane side is a multiple of 32): levels, reconstruction, SSE
+    q32s = [torch.empty((x.numel() // 1024, 32, 32), dtype=torch.int16, device="cuda") for x in xs]
+    for qp in (22, 27, 32, 37):
+        def fused32():
+            for x, o, q, s, h in zip(xs, outs, q32s, sses, heights):
+                adct.t32_encode_quant(x, qp, o, q=q, image_height=h, sse=s, stream=stream)
+
+        ms32 = timed(torch, fused32, 10, stream)
+        fused32()
+        sse32 = [s.cpu().numpy().astype(np.float64) for s in sses]
+        psnr32 = [10 * np.log10(255.0 ** 2 * n / np.maximum(e, 1)) for e, n in zip(sse32, npix)]
+        res["qp"][qp]["t32"] = {"ms": ms32, "blocks32_per_s": tiles / 4 / (ms32 * 1e-3),
+                                "gbs": 6144 * (tiles / 4) / (ms32 * 1e-3) / 1e9,
+                                "psnr_yuv_6_1_1_db": float(np.mean((6 * psnr32[0] + psnr32[1] + psnr32[2]) / 8))}
+    res["additions_per_sample_2d"] = {"t16": 2 * 44 / 16, "t8": 2 * 14 / 8, "t32": 2 * 120 / 32}
     res["bytes_per_region_mixed"] = MIXED_BYTES_PER_REGION
+    return res
+
+
+T32_RS = (4, 8, 16, 24, 32)
+
+
+def t32_images(torch, adct, stream, x, n_img):
+    """The 32-point extension on the batched images (32x32 blocks, 262144 of
+    them): per r the single-pass encoder keeping the top-left r x r
+    coefficients (int32 coefficients, reconstruction, per-image SSE), its
+    time and mean PSNR.  1024 + 4096 + 1024 bytes per 32x32 block."""
+    ntiles = x.numel() // 1024
+    coef = torch.empty((ntiles, 32, 32), dtype=torch.int32, device="cuda")
+    out = torch.empty_like(x)
+    sse = torch.empty(n_img, dtype=torch.int64, device="cuda")
+    res = {"blocks32": ntiles, "bytes_per_block32": 6144, "additions_per_32_point_transform": 120, "r": {}}
+    for r in T32_RS:
+        ms = timed(torch, lambda: adct.t32_encode_zonal(x, r, out, coef=coef, image_height=SIDE, sse=sse,
+                                                        stream=stream), 10, stream)
+        gbs = 6144 * ntiles / (ms * 1e-3) / 1e9
+        res["r"][r] = {"ms": ms, "blocks32_per_s": ntiles / (ms * 1e-3), "gbs": gbs, "frac_of_8tbs": gbs / HBM_PEAK_GBS,
+                       "psnr_db": float(np.mean(adct.psnr(sse.cpu().numpy(), SIDE * SIDE)))}
     return res
 
 
@@ -314,13 +354,15 @@ def uneven_batch(torch, adct, stream, n=4096):
     return out
 
 
-def serve_run(adct, mode, views, arr, tiles, warm):
+def serve_run(adct, mode, views, arr, tiles, warm, tune=None):
     """One server, every request replayed at its arrival time: p50 / p99 /
     mean latency (arrival to observed completion) and tiles/s from the first
-    counted arrival to the last completion, the first `warm` discarded."""
+    counted arrival to the last completion, the first `warm` discarded.
+    tune: the persistent loop's (tiles_per_item, wgs_per_cu)."""
     n_req = len(views)
+    tpi, wpc = tune if tune else (SERVE_TILES_PER_ITEM, SERVE_WGS_PER_CU)
     srv = adct.Server(pool_bytes=16 << 30, qp=27, mode=mode, max_inflight=512, max_requests=n_req,
-                      auto_release=True, tiles_per_item=SERVE_TILES_PER_ITEM, wgs_per_cu=SERVE_WGS_PER_CU,
+                      auto_release=True, tiles_per_item=tpi, wgs_per_cu=wpc,
                       dma_min_pixels=SERVE_DMA_MIN if mode == adct.SERVE_PERSISTENT else 0)
     t0 = adct.now_ns() + 20_000_000
     tickets = [srv.submit(v, t0 + int(a * 1e9)) for v, a in zip(views, arr)]
@@ -368,24 +410,38 @@ def serving(torch, adct, n_req, rates=(200, 500, 1000, 2000, 5000), warm=100):
     with torch.cuda.stream(cs):
         ms = timed(torch, lambda: dst.copy_(big, non_blocking=True), 10, cs)
     out = {"requests": n_req, "warmup_discarded": warm, "mean_tiles_per_request": float(tiles.mean()),
-           "h2d_gbs_pinned": big.numel() / (ms * 1e-3) / 1e9, "tiles_per_item": SERVE_TILES_PER_ITEM,
-           "wgs_per_cu": SERVE_WGS_PER_CU, "dma_min_pixels": SERVE_DMA_MIN, "rate": {}}
+           "h2d_gbs_pinned": big.numel() / (ms * 1e-3) / 1e9, "dma_min_pixels": SERVE_DMA_MIN, "rate": {}}
     modes = (("persistent", adct.SERVE_PERSISTENT), ("plain", adct.SERVE_PLAIN))
+    # the persistent loop's shape, searched as the batch autotuner searches
+    # its own: every candidate replays the first SERVE_TUNE_REQUESTS requests
+    # at 2000 req/s (their own arrival draw), and the lowest mean latency wins
+    n_tune = min(SERVE_TUNE_REQUESTS, n_req)
+    arr_t = synth.poisson_arrivals(2000.0, n_tune, seed=synth.SEED_ARRIVALS + 7)
+    search = {}
+    for tpi in SERVE_TUNE_TILES_PER_ITEM:
+        for wpc in SERVE_TUNE_WGS_PER_CU:
+            r = serve_run(adct, adct.SERVE_PERSISTENT, views[:n_tune], arr_t, tiles[:n_tune], min(warm, n_tune // 4),
+                          tune=(tpi, wpc))
+            search[f"{tpi}x{wpc}"] = {"mean_ms": r["mean_ms"], "p99_ms": r["p99_ms"]}
+    best = min(search, key=lambda k: search[k]["mean_ms"])
+    tune = tuple(int(v) for v in best.split("x"))
+    out["tune"] = {"tiles_per_item": tune[0], "wgs_per_cu": tune[1], "search": search,
+                   "objective": "mean latency at 2000 req/s"}
     for lam in rates:
         arr = synth.poisson_arrivals(float(lam), n_req)
-        out["rate"][lam] = {name: serve_run(adct, mode, views, arr, tiles, warm) for name, mode in modes}
+        out["rate"][lam] = {name: serve_run(adct, mode, views, arr, tiles, warm, tune) for name, mode in modes}
     # capacity: rates above the curve until p99 passes the bound, and a burst
     cap = {}
     for name, mode in modes:
         best, tried = None, {}
         for lam in CAPACITY_RATES:
             r = out["rate"][lam][name] if lam in out["rate"] else \
-                serve_run(adct, mode, views, synth.poisson_arrivals(float(lam), n_req), tiles, warm)
+                serve_run(adct, mode, views, synth.poisson_arrivals(float(lam), n_req), tiles, warm, tune)
             tried[lam] = {"p50_ms": r["p50_ms"], "p99_ms": r["p99_ms"], "tiles_per_s": r["tiles_per_s"]}
             if r["p99_ms"] > CAPACITY_P99_MS:
                 break
             best = lam
-        burst = serve_run(adct, mode, views, np.zeros(n_req), tiles, warm)
+        burst = serve_run(adct, mode, views, np.zeros(n_req), tiles, warm, tune)
         cap[name] = {"max_rate_p99_within_bound": best, "p99_bound_ms": CAPACITY_P99_MS,
                      "tiles_per_s": tried[best]["tiles_per_s"] if best else None, "tried": tried,
                      "burst_tiles_per_s": burst["tiles_per_s"], "burst_p99_ms": burst["p99_ms"]}
@@ -466,11 +522,16 @@ def summary_line(full: dict) -> dict:
             summ["serving_p50_p99_ms"] = {
                 str(lam): {m: [round(row[m]["p50_ms"], 3), round(row[m]["p99_ms"], 3)] for m in row}
                 for lam, row in sv["rate"].items()}
+            if "tune" in sv:
+                summ["serving_tune"] = {k: sv["tune"][k] for k in ("tiles_per_item", "wgs_per_cu")}
             if "capacity" in sv:
                 summ["serving_capacity"] = {m: {"max_req_per_s_p99_le_1ms": c["max_rate_p99_within_bound"],
                                                 "tiles_per_s": c["tiles_per_s"],
                                                 "burst_tiles_per_s": round(c["burst_tiles_per_s"])}
                                             for m, c in sv["capacity"].items()}
+        t = other.get("t32_images_1024x512x512")
+        if t:
+            summ["t32_zonal_frac"] = {str(r): round(v["frac_of_8tbs"], 3) for r, v in t["r"].items()}
         zz = other.get("image_experiment_zigzag_1024x512x512")
         if zz:
             summ["zigzag_psnr_db"] = {str(r): round(v["psnr_db"], 2) for r, v in zz["r"].items() if r in (10, 45, 150)}
@@ -624,6 +685,10 @@ def main():
         del coef, out, sse
         torch.cuda.empty_cache()
         other = {"image_experiment_zigzag_1024x512x512": zz}
+        t0 = time.perf_counter()
+        other["t32_images_1024x512x512"] = t32_images(torch, adct, stream, x, n_img)
+        other["t32_images_1024x512x512"]["wall_s"] = time.perf_counter() - t0
+        torch.cuda.empty_cache()
         for name, fn in (("single_image_256x256", lambda: single_image(torch, adct, stream)),
                          ("video_residuals_64x1920x1088", lambda: video(torch, adct, stream)),
                          ("uneven_batch_4096", lambda: uneven_batch(torch, adct, stream)),

@@ -437,6 +437,46 @@ __device__ __forceinline__ void store_row_fixed(char* p, const int32_t (&o)[16])
     }
 }
 
+// int16 output rows leave through LDS: each thread stages its two packed
+// rows (32 bytes each), then the workgroup stores 16-byte chunks with
+// consecutive threads on consecutive chunks of one sample row across the
+// group's tiles, so every store instruction writes whole contiguous lines.
+// Stored straight from the row role, each row would go out as two pieces
+// at a 32-byte stride, half of each line per instruction, which non-temporal
+// stores do not merge.  Staged rows: [sample row][tile][8 words + 4 pad].
+constexpr int kStageRowI16 = 12;
+
+template <int TPW>
+__device__ __forceinline__ void store_rows_i16(const GroupArgs& a, uint32_t g0, uint32_t ntile, uint32_t* lds,
+                                               int lt, int ip, const int32_t (&r0)[16], const int32_t (&r1)[16]) {
+    static_assert(16 * TPW * kStageRowI16 <= lds_words(TPW), "staging fits the group's LDS");
+    uint4* s0 = reinterpret_cast<uint4*>(lds + (ip * TPW + lt) * kStageRowI16);
+    uint4* s1 = reinterpret_cast<uint4*>(lds + ((ip + 8) * TPW + lt) * kStageRowI16);
+    uint32_t w[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) w[k] = pack_fixed_pair<int16_t>(r0[2 * k], r0[2 * k + 1]);
+    s0[0] = make_uint4(w[0], w[1], w[2], w[3]);
+    s0[1] = make_uint4(w[4], w[5], w[6], w[7]);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) w[k] = pack_fixed_pair<int16_t>(r1[2 * k], r1[2 * k + 1]);
+    s1[0] = make_uint4(w[0], w[1], w[2], w[3]);
+    s1[1] = make_uint4(w[4], w[5], w[6], w[7]);
+    __syncthreads();
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int c = tid + i * TPW * 8;  // chunk: (sample row, tile, half)
+        const int e = c >> 1, half = c & 1;
+        const int row = e / TPW, t = e % TPW;
+        if ((uint32_t)t < ntile) {
+            const uint32_t g = g0 + (uint32_t)t;
+            const uint32_t by = fdiv(g, a.bwdiv), bx = g - by * a.bw;
+            char* p = const_cast<char*>(row_ptr<int16_t>(a.dst, by, bx, row)) + 16 * half;
+            store16(p, *reinterpret_cast<const uint4*>(lds + e * kStageRowI16 + 4 * half));
+        }
+    }
+}
+
 // ---- per-image SSE accumulated across the groups of a workgroup ------------
 constexpr uint32_t kNoImage = 0xffffffffu;
 
@@ -603,15 +643,19 @@ __device__ __forceinline__ void process_group(const GroupArgs& a, uint32_t g0, u
         xf_inv<M::XF>(q, r1);
     }
     if constexpr (M::OUT == kOutBlocks) {
-        if (rok) {
-            int4* o0 = reinterpret_cast<int4*>(a.bout + (int64_t)rg * 256 + rip * 16);
-            int4* o1 = reinterpret_cast<int4*>(a.bout + (int64_t)rg * 256 + (rip + 8) * 16);
+        // the blocks leave through LDS as whole contiguous chunks (stored
+        // from the row role, a lane's 64-byte row would go out as four
+        // pieces, one per instruction, each a quarter of a line)
+        __syncthreads();  // every read of the inverse transpose is done
+        int4* l0 = reinterpret_cast<int4*>(lds + rlt * kIntTile + rip * kIntRow);
+        int4* l1 = reinterpret_cast<int4*>(lds + rlt * kIntTile + (rip + 8) * kIntRow);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                o0[k] = make_int4(r0[4 * k], r0[4 * k + 1], r0[4 * k + 2], r0[4 * k + 3]);
-                o1[k] = make_int4(r1[4 * k], r1[4 * k + 1], r1[4 * k + 2], r1[4 * k + 3]);
-            }
+        for (int k = 0; k < 4; ++k) {
+            l0[k] = make_int4(r0[4 * k], r0[4 * k + 1], r0[4 * k + 2], r0[4 * k + 3]);
+            l1[k] = make_int4(r1[4 * k], r1[4 * k + 1], r1[4 * k + 2], r1[4 * k + 3]);
         }
+        __syncthreads();
+        lds_blocks_to_global<TPW>(lds, tid, ntile, a.bout + (int64_t)g0 * 256);
         return;
     } else {
 #pragma unroll
@@ -619,10 +663,17 @@ __device__ __forceinline__ void process_group(const GroupArgs& a, uint32_t g0, u
             r0[j] = out_fixed<S>(r0[j]);
             r1[j] = out_fixed<S>(r1[j]);
         }
-        if (rok) {
-            char* pa = const_cast<char*>(row_ptr<S>(a.dst, rby, rbx, rip));
-            store_row_fixed<S>(pa, r0);
-            store_row_fixed<S>(pa + 8 * a.dst.pitch, r1);
+        if constexpr (sizeof(S) == 1) {
+            // one 16-byte piece per row: the lanes of a sample row store one
+            // contiguous run
+            if (rok) {
+                char* pa = const_cast<char*>(row_ptr<S>(a.dst, rby, rbx, rip));
+                store_row_fixed<S>(pa, r0);
+                store_row_fixed<S>(pa + 8 * a.dst.pitch, r1);
+            }
+        } else {
+            __syncthreads();  // every read of the inverse transpose is done
+            store_rows_i16<TPW>(a, g0, ntile, lds, rlt, rip, r0, r1);
         }
         if constexpr (M::SSE) {
           if (a.sse) {

@@ -84,30 +84,50 @@ __device__ __forceinline__ int32_t sample32(const Row32<S>& r, int j) {
         return (j & 1) ? ((int32_t)r.w[j >> 1] >> 16) : (int32_t)(int16_t)(r.w[j >> 1] & 0xffffu);
 }
 
+// The 32 output samples of a row as raw words, the layout of Row32.
 template <typename S>
-__device__ __forceinline__ void store_row32(char* p, const int32_t (&o)[32]) {
+__device__ __forceinline__ void pack_row32(const int32_t (&o)[32], uint32_t (&w)[Row32<S>::kWords]) {
     if constexpr (sizeof(S) == 1) {
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            uint32_t w[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int j = 16 * k + 4 * i;
-                w[i] = (uint32_t)o[j] | ((uint32_t)o[j + 1] << 8) | ((uint32_t)o[j + 2] << 16) |
-                       ((uint32_t)o[j + 3] << 24);
-            }
-            store16(p + 16 * k, make_uint4(w[0], w[1], w[2], w[3]));
-        }
+        for (int i = 0; i < 8; ++i)
+            w[i] = (uint32_t)o[4 * i] | ((uint32_t)o[4 * i + 1] << 8) | ((uint32_t)o[4 * i + 2] << 16) |
+                   ((uint32_t)o[4 * i + 3] << 24);
     } else {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            uint32_t w[4];
+        for (int i = 0; i < 16; ++i) w[i] = ((uint32_t)o[2 * i] & 0xffffu) | ((uint32_t)o[2 * i + 1] << 16);
+    }
+}
+
+// Output rows leave through LDS: each thread stages its packed row, then the
+// workgroup stores 16-byte chunks with consecutive threads on consecutive
+// chunks of a sample row (all 8 tiles' segments of that row in turn), so
+// every store instruction writes whole contiguous lines.  Stored straight
+// from the row role, each lane's row would go out as 2 (uint8) or 4 (int16)
+// pieces at a 32- or 64-byte stride, half or a quarter of each line per
+// instruction, which non-temporal stores do not merge: measured on MI355X,
+// the int16 codec ran 3 to 4.5 times slower that way.
+template <typename S>
+__device__ __forceinline__ void store_rows32(int32_t* lds, const uint32_t (&w)[Row32<S>::kWords], const Args32& a,
+                                             uint32_t g0, uint32_t ntile) {
+    constexpr int kW = Row32<S>::kWords;  // words per row segment
+    constexpr int kStride = kW + 4;       // LDS words per staged segment
+    constexpr int kChunks = kW / 4;       // 16-byte chunks per segment
+    const int tid = threadIdx.x;          // segment (row tid / 8, tile tid % 8)
+    uint4* st = reinterpret_cast<uint4*>(lds + tid * kStride);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int j = 8 * k + 2 * i;
-                w[i] = ((uint32_t)o[j] & 0xffffu) | ((uint32_t)o[j + 1] << 16);
-            }
-            store16(p + 16 * k, make_uint4(w[0], w[1], w[2], w[3]));
+    for (int k = 0; k < kChunks; ++k) st[k] = make_uint4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kChunks; ++i) {
+        const int c = tid + 256 * i;
+        const int seg = c / kChunks, k = c % kChunks;
+        const int t = seg & 7, row = seg >> 3;
+        if ((uint32_t)t < ntile) {
+            const uint32_t g = g0 + (uint32_t)t;
+            const uint32_t by = fdiv(g, a.bwdiv), bx = g - by * a.bw;
+            char* p = a.dst + (int64_t)(by * 32u + (uint32_t)row) * a.dst_pitch + (int64_t)bx * 32 * (int64_t)sizeof(S) +
+                      16 * k;
+            store16(p, *reinterpret_cast<const uint4*>(lds + seg * kStride + 4 * k));
         }
     }
 }
@@ -121,7 +141,7 @@ __device__ __forceinline__ void column_factors32(const Scale5& t, int v, float (
 
 template <typename S, int OP, bool STORE, bool SSE>
 __global__ __launch_bounds__(256) void k_t32(Args32 a) {
-    __shared__ int32_t lds[kTiles32 * kTile32];
+    __shared__ __align__(16) int32_t lds[kTiles32 * kTile32];
     __shared__ long long red[4];
     const int tid = threadIdx.x;
     const uint32_t group =
@@ -211,9 +231,12 @@ __global__ __launch_bounds__(256) void k_t32(Args32 a) {
     constexpr int32_t lo = sizeof(S) == 1 ? 0 : -255, hi = 255;
 #pragma unroll
     for (int j = 0; j < 32; ++j) R[j] = clamp_i32(R[j] >> 10, lo, hi);
-    if (rok)
-        store_row32<S>(a.dst + (int64_t)(by * 32u + (uint32_t)rr) * a.dst_pitch + (int64_t)bx * 32 * (int64_t)sizeof(S),
-                       R);
+    {
+        uint32_t w[Row32<S>::kWords];
+        pack_row32<S>(R, w);
+        __syncthreads();  // every read of the inverse transpose is done
+        store_rows32<S>(lds, w, a, g0, ntile);
+    }
     if constexpr (SSE) {
         int32_t s = 0;
         if (rok) {
@@ -243,9 +266,13 @@ __global__ __launch_bounds__(256) void k_t32(Args32 a) {
 }
 
 // T32^T Y T32 per block (block-major int32 in and out).
+constexpr int kInvRow = 36;                     // output staging: words per row
+constexpr int kInvTile = 32 * kInvRow + 4;      // and per tile
+
 __global__ __launch_bounds__(256) void k_t32_inv(const int32_t* __restrict__ in, int32_t* __restrict__ out,
                                                 uint32_t nblk) {
-    __shared__ int32_t lds[kTiles32 * kTile32];
+    __shared__ __align__(16) int32_t out_stage[kTiles32 * kInvTile];
+    int32_t* lds = out_stage;  // the transpose's [tile][row][33 words] fits the same array
     const int tid = threadIdx.x;
     const uint32_t g0 = blockIdx.x * (uint32_t)kTiles32;
     const uint32_t ntile = min((uint32_t)kTiles32, nblk - g0);
@@ -263,15 +290,29 @@ __global__ __launch_bounds__(256) void k_t32_inv(const int32_t* __restrict__ in,
     }
     __syncthreads();
     const int rt = tid & 7, rr = tid >> 3;
-    if ((uint32_t)rt >= ntile) return;
     int32_t c[32], R[32];
-    const int32_t* l = lds + rt * kTile32 + rr * kRow32;
+    {
+        const int32_t* l = lds + rt * kTile32 + rr * kRow32;
 #pragma unroll
-    for (int j = 0; j < 32; ++j) c[j] = l[j];
+        for (int j = 0; j < 32; ++j) c[j] = l[j];
+    }
     inv32(c, R);
-    int4* q = reinterpret_cast<int4*>(out + (int64_t)(g0 + (uint32_t)rt) * 1024 + rr * 32);
+    // the blocks leave through LDS as contiguous 16-byte chunks, whole lines
+    // per store instruction ([tile][row][32 words + 4 pad], tile stride
+    // 1156 words)
+    __syncthreads();
+    int4* st = reinterpret_cast<int4*>(out_stage + rt * kInvTile + rr * kInvRow);
 #pragma unroll
-    for (int k = 0; k < 8; ++k) q[k] = make_int4(R[4 * k], R[4 * k + 1], R[4 * k + 2], R[4 * k + 3]);
+    for (int k = 0; k < 8; ++k) st[k] = make_int4(R[4 * k], R[4 * k + 1], R[4 * k + 2], R[4 * k + 3]);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int ch = tid + 256 * i;
+        const int t = ch >> 8, row = (ch >> 3) & 31, k = ch & 7;
+        if ((uint32_t)t < ntile)
+            *reinterpret_cast<int4*>(out + (int64_t)(g0 + (uint32_t)t) * 1024 + row * 32 + 4 * k) =
+                *reinterpret_cast<const int4*>(out_stage + t * kInvTile + row * kInvRow + 4 * k);
+    }
 }
 
 __global__ __launch_bounds__(256) void k_t32_zero(unsigned long long* p, uint32_t n) {
