@@ -46,8 +46,8 @@ COPY_PROBE_BYTES = 1 << 30
 # reads half, and WRITE_SIZE all, of the bytes that the same counters give
 # for the 1 GiB device copy of that run, hence the scale factors.  Valid
 # only for the kernel sources the counters were taken on.
-ENC_TRAFFIC = {"sources_sha256": "f515cb7595eba5f90ed67045d297f06e5ee1ffc97c24762dcc43d0ea65016cf9",
-               "fetch_kib": 131708.2, "write_kib": 1312752.7, "fetch_scale": 2.0, "write_scale": 1.0}
+ENC_TRAFFIC = {"sources_sha256": "d436fffd5197086b2d7f5e4076471f735268ab1bbb3e709e838d2d49a57392b2",
+               "fetch_kib": 131661.3, "write_kib": 1312578.6, "fetch_scale": 2.0, "write_scale": 1.0}
 ENC_SOURCES = ("adct_butterfly.hpp", "adct_tile.hpp", "adct_core.hpp", "adct_plain.hip", "adct_internal.hpp",
                "adct_round.hpp")
 SERVE_TILES_PER_ITEM = 0     # persistent server: tiles per work item (0: chosen per request)
@@ -58,6 +58,9 @@ SERVE_TUNE_TILES_PER_ITEM = (0, 32, 64, 128)   # 0: chosen per request
 SERVE_TUNE_WGS_PER_CU = (1, 2, 4)
 CAPACITY_RATES = (5000, 7500, 10000, 15000, 20000)   # req/s, for the capacity search
 CAPACITY_P99_MS = 1.0
+
+
+LEGS = ("zigzag", "t32", "single", "video", "batch", "serving")
 
 
 def recon_bytes_per_tile(r: int) -> int:
@@ -74,6 +77,8 @@ def parse():
     ap.add_argument("--images", type=int, default=N_IMG)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-other", action="store_true", help="only the batched-image workload")
+    ap.add_argument("--legs", default=",".join(LEGS),
+                    help="comma-separated other workloads to run after the measured region: " + ", ".join(LEGS))
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--detail", default=os.path.join(ROOT, "gpurun_out", "bench_detail.json"),
                     help="JSON file for the full results (the stdout line holds a summary)")
@@ -678,24 +683,27 @@ def main():
     del copies
     torch.cuda.empty_cache()
     if not args.no_other:
-        t0 = time.perf_counter()
-        zz = image_experiment(torch, adct, stream, x, coef, out, n_img)
-        zz["wall_s"] = time.perf_counter() - t0
-        print(f"[bench] image_experiment_zigzag done in {zz['wall_s']:.1f} s", file=sys.stderr, flush=True)
-        del coef, out, sse
-        torch.cuda.empty_cache()
-        other = {"image_experiment_zigzag_1024x512x512": zz}
-        t0 = time.perf_counter()
-        other["t32_images_1024x512x512"] = t32_images(torch, adct, stream, x, n_img)
-        other["t32_images_1024x512x512"]["wall_s"] = time.perf_counter() - t0
-        torch.cuda.empty_cache()
-        for name, fn in (("single_image_256x256", lambda: single_image(torch, adct, stream)),
-                         ("video_residuals_64x1920x1088", lambda: video(torch, adct, stream)),
-                         ("uneven_batch_4096", lambda: uneven_batch(torch, adct, stream)),
-                         ("serving_poisson", lambda: serving(torch, adct, args.serve_requests))):
+        legs = [g for g in args.legs.split(",") if g]
+        unknown = [g for g in legs if g not in LEGS]
+        if unknown:
+            print(f"[bench] unknown legs {unknown}; choose from {list(LEGS)}", file=sys.stderr, flush=True)
+            sys.exit(2)
+        other = {}
+        for leg, name, fn in (
+                ("zigzag", "image_experiment_zigzag_1024x512x512",
+                 lambda: image_experiment(torch, adct, stream, x, coef, out, n_img)),
+                ("t32", "t32_images_1024x512x512", lambda: t32_images(torch, adct, stream, x, n_img)),
+                ("single", "single_image_256x256", lambda: single_image(torch, adct, stream)),
+                ("video", "video_residuals_64x1920x1088", lambda: video(torch, adct, stream)),
+                ("batch", "uneven_batch_4096", lambda: uneven_batch(torch, adct, stream)),
+                ("serving", "serving_poisson", lambda: serving(torch, adct, args.serve_requests))):
+            if leg not in legs:
+                continue
             t0 = time.perf_counter()
             other[name] = fn()
             other[name]["wall_s"] = time.perf_counter() - t0
+            if leg == "t32":  # the last leg on the batched images
+                del coef, out, sse
             torch.cuda.empty_cache()
             print(f"[bench] {name} done in {other[name]['wall_s']:.1f} s", file=sys.stderr, flush=True)
         full["other_workloads"] = other
