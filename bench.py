@@ -52,7 +52,8 @@ ENC_SOURCES = ("adct_butterfly.hpp", "adct_tile.hpp", "adct_core.hpp", "adct_pla
                "adct_round.hpp")
 SERVE_TILES_PER_ITEM = 0     # persistent server: tiles per work item (0: chosen per request)
 SERVE_WGS_PER_CU = 2         # persistent server: loop workgroups per CU
-SERVE_DMA_MIN = 0            # persistent server: DMA copy from this many pixels (0: the library default)
+SERVE_DMA_MIN = 0            # persistent server: large requests from this many pixels (0: the library default)
+SERVE_POLICY_RATES = (200, 2000)  # rates at which the adaptive DMA routing is compared with routing by size
 SERVE_TUNE_REQUESTS = 600    # requests replayed per candidate of the loop-shape search
 SERVE_TUNE_TILES_PER_ITEM = (0, 32, 64, 128)   # 0: chosen per request
 SERVE_TUNE_WGS_PER_CU = (1, 2, 4)
@@ -359,16 +360,18 @@ def uneven_batch(torch, adct, stream, n=4096):
     return out
 
 
-def serve_run(adct, mode, views, arr, tiles, warm, tune=None):
+def serve_run(adct, mode, views, arr, tiles, warm, tune=None, dma_policy=0):
     """One server, every request replayed at its arrival time: p50 / p99 /
     mean latency (arrival to observed completion) and tiles/s from the first
     counted arrival to the last completion, the first `warm` discarded.
-    tune: the persistent loop's (tiles_per_item, wgs_per_cu)."""
+    tune: the persistent loop's (tiles_per_item, wgs_per_cu); dma_policy:
+    which requests the persistent server copies by DMA."""
     n_req = len(views)
     tpi, wpc = tune if tune else (SERVE_TILES_PER_ITEM, SERVE_WGS_PER_CU)
+    persistent = mode == adct.SERVE_PERSISTENT
     srv = adct.Server(pool_bytes=16 << 30, qp=27, mode=mode, max_inflight=512, max_requests=n_req,
                       auto_release=True, tiles_per_item=tpi, wgs_per_cu=wpc,
-                      dma_min_pixels=SERVE_DMA_MIN if mode == adct.SERVE_PERSISTENT else 0)
+                      dma_min_pixels=SERVE_DMA_MIN if persistent else 0, dma_policy=dma_policy if persistent else 0)
     t0 = adct.now_ns() + 20_000_000
     tickets = [srv.submit(v, t0 + int(a * 1e9)) for v, a in zip(views, arr)]
     srv.wait_all(600)
@@ -384,7 +387,8 @@ def serve_run(adct, mode, views, arr, tiles, warm, tune=None):
     srv.close()
     return {"p50_ms": adct.percentile(lat, 50), "p99_ms": adct.percentile(lat, 99), "mean_ms": float(np.mean(lat)),
             "tiles_per_s": float(tiles[warm:].sum() / ((last - first) * 1e-9)),
-            "loop_launches": st["loop_launches"], "pool_high_water": st["pool_high_water"]}
+            "loop_launches": st["loop_launches"], "pool_high_water": st["pool_high_water"],
+            "dma_copies": st["dma_copies"]}
 
 
 def serving(torch, adct, n_req, rates=(200, 500, 1000, 2000, 5000), warm=100):
@@ -435,6 +439,17 @@ def serving(torch, adct, n_req, rates=(200, 500, 1000, 2000, 5000), warm=100):
     for lam in rates:
         arr = synth.poisson_arrivals(float(lam), n_req)
         out["rate"][lam] = {name: serve_run(adct, mode, views, arr, tiles, warm, tune) for name, mode in modes}
+    # the persistent server with every large request copied by DMA (routing
+    # by size) against the adaptive routing above, on the same arrivals
+    pol = {}
+    for lam in SERVE_POLICY_RATES:
+        if lam in out["rate"]:
+            r = serve_run(adct, adct.SERVE_PERSISTENT, views, synth.poisson_arrivals(float(lam), n_req), tiles, warm,
+                          tune, dma_policy=adct.SERVE_DMA_BY_SIZE)
+            a = out["rate"][lam]["persistent"]
+            pol[lam] = {"adaptive": {k: a[k] for k in ("p50_ms", "p99_ms", "mean_ms", "dma_copies")},
+                        "by_size": {k: r[k] for k in ("p50_ms", "p99_ms", "mean_ms", "dma_copies")}}
+    out["dma_policy"] = pol
     # capacity: rates above the curve until p99 passes the bound, and a burst
     cap = {}
     for name, mode in modes:
@@ -534,6 +549,10 @@ def summary_line(full: dict) -> dict:
                                                 "tiles_per_s": c["tiles_per_s"],
                                                 "burst_tiles_per_s": round(c["burst_tiles_per_s"])}
                                             for m, c in sv["capacity"].items()}
+            if sv.get("dma_policy"):
+                summ["serving_p99_ms_dma_adaptive_vs_by_size"] = {
+                    str(lam): [round(v["adaptive"]["p99_ms"], 3), round(v["by_size"]["p99_ms"], 3)]
+                    for lam, v in sv["dma_policy"].items()}
         t = other.get("t32_images_1024x512x512")
         if t:
             summ["t32_zonal_frac"] = {str(r): round(v["frac_of_8tbs"], 3) for r, v in t["r"].items()}

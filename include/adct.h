@@ -520,10 +520,10 @@ int adct_autotune(int32_t op, int32_t param, const adct_job* jobs, int32_t njobs
  * contiguous runs and code them from there, so requests that arrive while
  * others run are coded alongside them; the last workgroup to finish a
  * request posts its SSE and a completion flag to host memory.  Requests of
- * at least dma_min_pixels pixels are instead copied into the pool by the
- * DMA engine, on a second stream, and published once that copy is done
- * (the engine moves a large request over the host link faster than the
- * loop's own reads, which then code).  In ADCT_SERVE_PLAIN mode the same
+ * at least dma_min_pixels pixels that arrive while others are in flight are
+ * instead copied into the pool by the DMA engine, on a second stream, and
+ * published once that copy is done, so that their transfer neither waits
+ * for the loop's staging of the others nor holds it up (dma_policy).  In ADCT_SERVE_PLAIN mode the same
  * admission feeds a plain per-request path instead (one stream, first in
  * first out: copy in, adct_fwd2d_quant, adct_dequant_recon, SSE copy back,
  * event), the baseline the persistent loop is measured against.  In both
@@ -556,15 +556,23 @@ typedef struct adct_server_cfg {
                                 loop ends; the server relaunches it when work
                                 reappears (0 = 100000)                           */
     int32_t dma_min_pixels;  /* persistent: requests of at least this many
-                                pixels are copied into the pool by the DMA
-                                engine (one copy on a second stream) and
-                                published to the loop once the copy is done;
-                                smaller ones are staged by the loop itself.
-                                0 = ADCT_SERVE_DMA_MIN_DEFAULT, -1 = never       */
-    int32_t reserved;
+                                pixels are "large"; a request copied into the
+                                pool by the DMA engine (one copy on a second
+                                stream) is published to the loop once the copy
+                                is done, the others are staged by the loop.
+                                0 = ADCT_SERVE_DMA_MIN_DEFAULT, -1 = no DMA      */
+    int32_t dma_policy;      /* persistent: which requests go by DMA.
+                                ADCT_SERVE_DMA_ADAPTIVE (0): a large request
+                                when others are in flight (alone, the loop
+                                stages it and codes while it crosses the link),
+                                and a smaller one while the loop stages a large
+                                one; ADCT_SERVE_DMA_BY_SIZE (1): every large
+                                request                                          */
 } adct_server_cfg;
 
 #define ADCT_SERVE_DMA_MIN_DEFAULT (2048 * 2048)
+#define ADCT_SERVE_DMA_ADAPTIVE 0
+#define ADCT_SERVE_DMA_BY_SIZE  1
 
 typedef struct adct_result {
     int32_t status;          /* ADCT_OK, ADCT_PENDING or ADCT_E_STOPPED          */
@@ -589,6 +597,8 @@ typedef struct adct_stats {
     double latency_p50_ms, latency_p99_ms, latency_mean_ms, latency_max_ms;
     double queue_p50_ms, queue_p99_ms;  /* arrival to admission                  */
     int64_t loop_launches;   /* persistent loop (re)launches                     */
+    int64_t dma_copies;      /* persistent: requests copied into the pool by the
+                                DMA engine (the rest were staged by the loop)    */
 } adct_stats;
 
 typedef struct adct_server adct_server;

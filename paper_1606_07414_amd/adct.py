@@ -49,6 +49,7 @@ OP_ZONAL, OP_QUANT, OP_ZIGZAG = 1, 2, 3
 XF_PROPOSED, XF_WHT, XF_DCT = 0, 1, 2
 KEEP_ZONAL, KEEP_ZIGZAG = 0, 1
 SERVE_PERSISTENT, SERVE_PLAIN = 0, 1
+SERVE_DMA_ADAPTIVE, SERVE_DMA_BY_SIZE = 0, 1
 
 
 class ServerCfg(ctypes.Structure):
@@ -56,7 +57,7 @@ class ServerCfg(ctypes.Structure):
                 ("max_inflight", ctypes.c_int32), ("max_requests", ctypes.c_int32),
                 ("auto_release", ctypes.c_int32), ("tiles_per_item", ctypes.c_int32),
                 ("wgs_per_cu", ctypes.c_int32), ("idle_polls", ctypes.c_int32),
-                ("dma_min_pixels", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("dma_min_pixels", ctypes.c_int32), ("dma_policy", ctypes.c_int32)]
 
 
 class Result(ctypes.Structure):
@@ -73,7 +74,8 @@ class Stats(ctypes.Structure):
                 ("tiles_per_s", ctypes.c_double), ("latency_p50_ms", ctypes.c_double),
                 ("latency_p99_ms", ctypes.c_double), ("latency_mean_ms", ctypes.c_double),
                 ("latency_max_ms", ctypes.c_double), ("queue_p50_ms", ctypes.c_double),
-                ("queue_p99_ms", ctypes.c_double), ("loop_launches", ctypes.c_int64)]
+                ("queue_p99_ms", ctypes.c_double), ("loop_launches", ctypes.c_int64),
+                ("dma_copies", ctypes.c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -742,9 +744,10 @@ class Server:
 
     def __init__(self, pool_bytes: int, qp: int = 27, mode: int = SERVE_PERSISTENT, max_inflight: int = 64,
                  max_requests: int = 4096, auto_release: bool = False, tiles_per_item: int = 0,
-                 wgs_per_cu: int = 0, idle_polls: int = 0, dma_min_pixels: int = 0):
+                 wgs_per_cu: int = 0, idle_polls: int = 0, dma_min_pixels: int = 0,
+                 dma_policy: int = 0):
         cfg = ServerCfg(pool_bytes, qp, mode, max_inflight, max_requests, 1 if auto_release else 0, tiles_per_item,
-                        wgs_per_cu, idle_polls, dma_min_pixels, 0)
+                        wgs_per_cu, idle_polls, dma_min_pixels, dma_policy)
         h = _P()
         _check(_lib().adct_server_create(ctypes.byref(h), ctypes.byref(cfg)), "server_create")
         self._h = h

@@ -11,11 +11,11 @@
 // first copies its own sample rows over the host link into the request's
 // pool block, in long contiguous runs, and is then coded from there.  Items
 // are staged in slot order, at most kStagers at a time, and the coding of
-// one item overlaps the transfer of others.  A large request (at least
-// dma_min_pixels) is instead copied into its pool block by the DMA engine on
-// a second stream and published, with no host address, once the host sees
-// that copy's event: the engine moves long transfers over the link faster
-// than the loop's reads do.  Results (levels and reconstruction) go to the
+// one item overlaps the transfer of others.  A request may instead be
+// copied into its pool block by the DMA engine on a second stream and
+// published, with no host address, once the host sees that copy's event
+// (route_dma decides which, from the request's size and what is in
+// flight).  Results (levels and reconstruction) go to the
 // request's block of the device pool.
 //
 // Loop kernel (persistent).  Workgroup 0 is the dispatcher: one wave polls
@@ -363,6 +363,7 @@ struct Req {
     int state = kWaiting;
     int ev = -1;  // plain: event slot marking the end of the request;
                   // persistent: event slot marking the end of its DMA copy
+    bool big_staged = false;  // persistent: a large request staged by the loop
 };
 
 // Pool block of a request: the copied source, the reconstruction and the
@@ -407,6 +408,8 @@ struct adct_server {
     // persistent mode
     hipStream_t copy_stream = nullptr; // DMA copies of large requests
     std::vector<int64_t> dma_pending; // copies issued, not yet published (issue order)
+    int64_t big_staging = 0;          // large requests in flight that the loop stages
+    int64_t dma_copies = 0;           // requests copied by the DMA engine
     ReqDesc* h_desc = nullptr;        // host-mapped descriptor ring, by slot
     ReqDesc* d_hdesc = nullptr;       // its device address
     uint32_t* h_count = nullptr;      // host-mapped slot count
@@ -519,10 +522,29 @@ void copy_in(adct_server* S, const Req& r, const Block& b, hipStream_t stream) {
 bool event_done(adct_server* S, int ev);
 void publish(adct_server* S, int64_t k, uint64_t hsrc);
 
+// Persistent mode: whether request r goes to the pool by a DMA copy rather
+// than through the loop's own staging (called with mu held).
+//   ADCT_SERVE_DMA_BY_SIZE: exactly the requests of at least dma_min_pixels.
+//   ADCT_SERVE_DMA_ADAPTIVE: a large request (at least dma_min_pixels) is
+//   staged by the loop when nothing else is in flight -- the loop's reads
+//   reach the link's rate on one long request and its coding overlaps them,
+//   where a DMA copy must end before any coding starts -- and copied by DMA
+//   when other requests are in flight, so that it neither waits for their
+//   staging nor holds theirs up.  A smaller request is staged by the loop,
+//   unless the loop is staging a large one: staging goes in order, and
+//   behind that one it would wait for the whole transfer, so it is copied
+//   by DMA alongside it instead.
+bool route_dma(const adct_server* S, const Req& r) {
+    if (S->cfg.dma_min_pixels <= 0) return false;
+    const bool big = (int64_t)r.h * r.w >= S->cfg.dma_min_pixels;
+    if (S->cfg.dma_policy == ADCT_SERVE_DMA_BY_SIZE) return big;
+    return big ? !S->running.empty() : S->big_staging > 0;
+}
+
 // Hands an admitted request to the device (called with mu held).  Persistent
-// mode: publish its descriptor, or for a large request start its DMA copy
-// into the pool (published when done); plain mode: copy in, code, copy the
-// SSE back and record an event, all on the one stream.
+// mode: publish its descriptor, or start its DMA copy into the pool
+// (published when done); plain mode: copy in, code, copy the SSE back and
+// record an event, all on the one stream.
 void issue(adct_server* S, int64_t k) {
     Req& r = S->reqs[(size_t)k];
     const Block b = block_of(S, r);
@@ -540,14 +562,17 @@ void issue(adct_server* S, int64_t k) {
         r.ev = S->free_events.back();
         S->free_events.pop_back();
         hip_ok(S, hipEventRecord(S->events[(size_t)r.ev], S->stream));
-    } else if (S->cfg.dma_min_pixels > 0 && (int64_t)r.h * r.w >= S->cfg.dma_min_pixels) {
+    } else if (route_dma(S, r)) {
         // the DMA engine copies it into the pool; published when done
         copy_in(S, r, b, S->copy_stream);
+        ++S->dma_copies;
         r.ev = S->free_events.back();
         S->free_events.pop_back();
         hip_ok(S, hipEventRecord(S->events[(size_t)r.ev], S->copy_stream));
         S->dma_pending.push_back(k);
     } else {
+        r.big_staged = S->cfg.dma_min_pixels > 0 && (int64_t)r.h * r.w >= S->cfg.dma_min_pixels;
+        if (r.big_staged) ++S->big_staging;
         publish(S, k, r.dev_src);
     }
     r.state = kRunning;
@@ -628,6 +653,10 @@ void finish(adct_server* S, int64_t k, int64_t now) {
     r.sse = __atomic_load_n(&S->h_comp[k].sse, __ATOMIC_ACQUIRE);
     r.t_done = now;
     r.state = kDone;
+    if (r.big_staged) {
+        r.big_staged = false;
+        --S->big_staging;
+    }
     if (r.ev >= 0) {
         S->free_events.push_back(r.ev);
         r.ev = -1;
@@ -744,6 +773,7 @@ int adct_server_create(adct_server** out, const adct_server_cfg* cfg_in) {
     if (cfg.wgs_per_cu == 0) cfg.wgs_per_cu = 2;
     if (cfg.idle_polls == 0) cfg.idle_polls = 100000;
     if (cfg.dma_min_pixels == 0) cfg.dma_min_pixels = ADCT_SERVE_DMA_MIN_DEFAULT;
+    if (cfg.dma_policy != ADCT_SERVE_DMA_ADAPTIVE && cfg.dma_policy != ADCT_SERVE_DMA_BY_SIZE) return ADCT_E_ARG;
     if (cfg.pool_bytes < 1024 || cfg.max_inflight < 1 || cfg.max_requests < 1 || cfg.tiles_per_item < 0 ||
         cfg.tiles_per_item % 16 || cfg.wgs_per_cu < 1 || cfg.wgs_per_cu > 8 || cfg.idle_polls < 1 ||
         cfg.dma_min_pixels < -1 ||
@@ -925,6 +955,7 @@ int adct_server_stats(adct_server* S, adct_stats* out) {
     out->pool_bytes = S->pool->capacity();
     out->pool_high_water = S->pool->high_water();
     out->loop_launches = S->loop_launches;
+    out->dma_copies = S->dma_copies;
     if (!lat.empty()) {
         out->wall_s = (double)(t_last - t_first) * 1e-9;
         out->tiles_per_s = out->wall_s > 0 ? (double)out->tiles_completed / out->wall_s : 0.0;

@@ -450,3 +450,13 @@ def test_t32_kernel_butterflies_count_120_and_match_oracle():
         assert n == 120 and np.array_equal(y, A @ v)
         x, n = adct.t32_host_butterfly_count(v, inverse=True)
         assert n == 120 and np.array_equal(x, A.T @ v)
+
+
+def test_serving_constants_match_header():
+    import re
+    with open(os.path.join(ROOT, "include", "adct.h")) as f:
+        defs = dict(re.findall(r"#define ADCT_(SERVE_[A-Z_]+)\s+(\d+)\s*$", f.read(), re.M))
+    for name in ("SERVE_PERSISTENT", "SERVE_PLAIN", "SERVE_DMA_ADAPTIVE", "SERVE_DMA_BY_SIZE"):
+        assert int(defs[name]) == getattr(adct, name), name
+    assert len(adct.ServerCfg._fields_) == 11 and adct.ServerCfg._fields_[-1][0] == "dma_policy"
+    assert adct.Stats._fields_[-1][0] == "dma_copies"

@@ -36,7 +36,10 @@ def _full_result():
                                                  "burst_p99_ms": 50.0,
                                                  "tried": {lam: {"p50_ms": 0.1, "p99_ms": 0.5, "tiles_per_s": 1e8}
                                                            for lam in bench.CAPACITY_RATES}}
-                                             for m in ("persistent", "plain")}},
+                                             for m in ("persistent", "plain")},
+                                "dma_policy": {lam: {pol: {"p50_ms": 0.05, "p99_ms": 0.36, "mean_ms": 0.1,
+                                                           "dma_copies": 400} for pol in ("adaptive", "by_size")}
+                                               for lam in bench.SERVE_POLICY_RATES}},
             "image_experiment_zigzag_1024x512x512": {"r": {r: {"psnr_db": 30.0} for r in bench.ZIGZAG_R}},
         },
         "detail_file": "gpurun_out/bench_detail.json",
@@ -55,6 +58,8 @@ def test_summary_line_is_compact_and_complete():
         assert k in line["roofline"], k
     assert set(line["cpu_baseline"]) == {"value", "unit", "cores", "kind", "sample"}
     assert "\n" not in text
+    assert set(line["other_workloads"]["serving_p99_ms_dma_adaptive_vs_by_size"]) == \
+        {str(lam) for lam in bench.SERVE_POLICY_RATES}
 
 
 def test_summary_line_without_other_workloads():

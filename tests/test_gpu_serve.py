@@ -253,20 +253,53 @@ def test_benchmark_configuration_full_size_requests(mode):
     srv.close()
 
 
-@pytest.mark.parametrize("dma_min", [1, 512 * 512, -1])
-def test_dma_copied_requests_match_alone(dma_min):
-    # dma_min_pixels = 1: every request is copied into the pool by the DMA
-    # engine and published afterwards; 512 x 512: a mix of DMA-copied and
-    # loop-staged requests in one stream of arrivals; -1: none is copied
+@pytest.mark.parametrize("dma_min,policy", [(1, adct.SERVE_DMA_BY_SIZE), (512 * 512, adct.SERVE_DMA_BY_SIZE),
+                                            (-1, adct.SERVE_DMA_ADAPTIVE), (512 * 512, adct.SERVE_DMA_ADAPTIVE),
+                                            (1, adct.SERVE_DMA_ADAPTIVE)])
+def test_dma_copied_requests_match_alone(dma_min, policy):
+    # by size, dma_min_pixels = 1: every request is copied into the pool by
+    # the DMA engine and published afterwards; 512 x 512: a mix of DMA-copied
+    # and loop-staged requests in one stream of arrivals; -1: none is copied;
+    # adaptive: the routing depends on what is in flight at each admission
     imgs, pins = _requests(60, 256, 1024, seed=29_000)
     arr = synth.poisson_arrivals(3000.0, len(pins), seed=29_001)
-    srv = adct.Server(pool_bytes=1 << 30, qp=QP, max_inflight=64, max_requests=64, dma_min_pixels=dma_min)
+    srv = adct.Server(pool_bytes=1 << 30, qp=QP, max_inflight=64, max_requests=64, dma_min_pixels=dma_min,
+                      dma_policy=policy)
     t0 = adct.now_ns() + 2_000_000
     tickets = [srv.submit(p, t0 + int(a * 1e9)) for p, a in zip(pins, arr)]
     srv.wait_all(60)
     st = srv.stats()
     assert st["completed"] == 60 and st["cancelled"] == 0
+    if dma_min == 1 and policy == adct.SERVE_DMA_BY_SIZE:
+        assert st["dma_copies"] == 60
+    if dma_min == -1:
+        assert st["dma_copies"] == 0
     _check_all(srv, tickets, imgs, oracle_every=29)
+    srv.close()
+
+
+def test_adaptive_routing():
+    # dma_min_pixels = 512^2, adaptive.  A large request alone is staged by
+    # the loop.  Requests arriving together are admitted in one pass: the
+    # first large one finds nothing in flight (staged), the next large one
+    # finds it in flight (DMA), and the small ones find a large one being
+    # staged (DMA).  Then a small request alone is staged.
+    big = [synth.ar1_image(29_900 + k, 768, 768) for k in range(2)]
+    small = [synth.ar1_image(29_910 + k, 256, 256) for k in range(3)]
+    srv = adct.Server(pool_bytes=1 << 30, qp=QP, max_inflight=64, max_requests=16, dma_min_pixels=512 * 512)
+    pins = [torch.from_numpy(i).pin_memory() for i in big + small]
+    t = srv.submit(pins[0])
+    srv.wait_all(30)
+    assert srv.stats()["dma_copies"] == 0
+    t0 = adct.now_ns() + 50_000_000
+    tickets = [srv.submit(p, t0) for p in (pins[0], pins[2], pins[1], pins[3], pins[4])]
+    srv.wait_all(30)
+    assert srv.stats()["dma_copies"] == 4
+    t_last = srv.submit(pins[2])
+    srv.wait_all(30)
+    assert srv.stats()["dma_copies"] == 4
+    imgs = [big[0], big[0], small[0], big[1], small[1], small[2], small[0]]
+    _check_all(srv, [t] + tickets + [t_last], imgs, oracle_every=3)
     srv.close()
 
 
@@ -276,7 +309,8 @@ def test_dma_copied_pitched_request_and_pool_reuse():
     img = synth.ar1_image(29_500, 256, 320)
     wide = torch.zeros((256, 384), dtype=torch.uint8).pin_memory()
     wide[:, 16:336] = torch.from_numpy(img)
-    srv = adct.Server(pool_bytes=1 << 20, qp=QP, max_inflight=1, max_requests=8, dma_min_pixels=1)
+    srv = adct.Server(pool_bytes=1 << 20, qp=QP, max_inflight=1, max_requests=8, dma_min_pixels=1,
+                      dma_policy=adct.SERVE_DMA_BY_SIZE)
     t = srv.submit(wide[:, 16:336])
     srv.wait_all(30)
     _check_all(srv, [t], [img], oracle_every=1)
@@ -286,10 +320,14 @@ def test_dma_copied_pitched_request_and_pool_reuse():
         while srv.poll(tk)[0] == adct.PENDING:
             time.sleep(0.001)
         _check_all(srv, [tk], [imgs[k]])
+    assert srv.stats()["dma_copies"] == 5
     srv.close()
 
 
-def test_server_rejects_bad_dma_threshold():
+def test_server_rejects_bad_dma_threshold_and_policy():
     with pytest.raises(adct.AdctError) as e:
         adct.Server(pool_bytes=1 << 20, qp=QP, max_requests=4, dma_min_pixels=-2)
+    assert e.value.code == adct.E_ARG
+    with pytest.raises(adct.AdctError) as e:
+        adct.Server(pool_bytes=1 << 20, qp=QP, max_requests=4, dma_policy=2)
     assert e.value.code == adct.E_ARG
