@@ -36,6 +36,11 @@ class Job(ctypes.Structure):
     _fields_ = [("src", Plane), ("dst", Plane), ("coef", ctypes.c_void_p), ("sse", ctypes.c_void_p)]
 
 
+class QuantJob(ctypes.Structure):
+    _fields_ = [("src", Plane), ("dst", Plane), ("q", ctypes.c_void_p), ("sse", ctypes.c_void_p),
+                ("image_height", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 class Tune(ctypes.Structure):
     _fields_ = [("tiles_per_group", ctypes.c_int32), ("groups_per_item", ctypes.c_int32),
                 ("wgs_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32)]
@@ -127,6 +132,7 @@ _SIGNATURES = {
     "adct_dequant_recon": (ctypes.c_int, [_P, ctypes.c_int, _PP, _PP, _I32, _P, _P]),
     "adct_encode_zonal": (ctypes.c_int, [_PP, ctypes.c_int, _P, _PP, _I32, _P, _P]),
     "adct_encode_quant": (ctypes.c_int, [_PP, ctypes.c_int, _P, _PP, _I32, _P, _P]),
+    "adct_encode_quant_planes": (ctypes.c_int, [_P, _I32, ctypes.c_int, _P]),
     "adct_default_tune": (ctypes.c_int, [ctypes.POINTER(Tune)]),
     "adct_work_queue": (ctypes.c_int, [_P, _I32, _I32, _I32, _P, _I64, ctypes.POINTER(_I64)]),
     "adct_batch_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.POINTER(Job), _I32, _I32, _I32,
@@ -626,6 +632,26 @@ def encode_quant(src, qp: int, dst, q=None, image_height=None, sse=None, want_ss
     _check(_lib().adct_encode_quant(ctypes.byref(ps), qp, q.data_ptr() if q is not None else None,
                                     ctypes.byref(pd), ih, sp, _stream(stream)), "encode_quant")
     return sse
+
+
+def encode_quant_planes(jobs, qp: int, want_sse=True, stream=None):
+    """adct_encode_quant over several planes in one launch.  jobs: a list of
+    (src, dst, q, image_height, sse) with q, image_height and sse optional
+    (q None for all jobs or for none; sse allocated when None and want_sse).
+    Returns the list of per-image SSE tensors (None entries when not wanted)."""
+    arr = (QuantJob * max(1, len(jobs)))()
+    keep, out = [], []
+    for i, job in enumerate(jobs):
+        src, dst = job[0], job[1]
+        q = job[2] if len(job) > 2 else None
+        ih = job[3] if len(job) > 3 else None
+        sse_t = job[4] if len(job) > 4 else None
+        ih, sse_t, sp = _sse_out(src, ih, sse_t, want_sse)
+        arr[i] = QuantJob(plane(src), plane(dst), q.data_ptr() if q is not None else None, sp, ih, 0)
+        keep.append((src, dst, q, sse_t))
+        out.append(sse_t)
+    _check(_lib().adct_encode_quant_planes(arr, len(jobs), qp, _stream(stream)), "encode_quant_planes")
+    return out
 
 
 def sse(a, b, image_height=None, out=None, stream=None):

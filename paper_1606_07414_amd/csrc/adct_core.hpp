@@ -741,14 +741,14 @@ constexpr uint32_t kSseSpreadMin = ADCT_SSE_SPREAD_MIN;
 // PF = false is the form for gpw == 1: with no next group to prefetch, no
 // registers are held for one while the group is coded, which keeps the SSE
 // modes at 5 waves per SIMD instead of 4.
+// `qs`, `dqs`: as for process_group.
 template <int TPW, typename S, typename M, bool PF>
-__global__ __launch_bounds__(TPW * 8) void k_group(GroupArgs a, uint32_t nblk, uint32_t gpw, uint32_t spread_rows) {
-    __shared__ uint32_t lds[lds_words(TPW)];
-    __shared__ long long red[TPW * 8 / 64];
+__device__ __forceinline__ void group_chunk(const GroupArgs& a, uint32_t nblk, uint32_t gpw, uint32_t spread_rows,
+                                            uint32_t b, uint32_t* lds, long long* red, const Scale5& qs,
+                                            const Scale5& dqs) {
     SseAcc acc{0, kNoImage};
     RowWords rows;
-    const uint32_t chunk =
-        spread_rows ? (blockIdx.x % kSseSpread) * spread_rows + blockIdx.x / kSseSpread : blockIdx.x;
+    const uint32_t chunk = spread_rows ? (b % kSseSpread) * spread_rows + b / kSseSpread : b;
     uint32_t g0 = chunk * gpw * (uint32_t)TPW;
     if (g0 >= nblk) return;
     if constexpr (M::IN == kInSamples) load_group_rows<TPW, S>(a, g0, min((uint32_t)TPW, nblk - g0), rows);
@@ -758,16 +758,49 @@ __global__ __launch_bounds__(TPW * 8) void k_group(GroupArgs a, uint32_t nblk, u
             if (k) __syncthreads();  // the previous group's LDS reads are done
             const uint32_t g0n = g0 + (uint32_t)TPW;
             const uint32_t ntn = g0n < gend ? min((uint32_t)TPW, gend - g0n) : 0u;
-            process_group<TPW, S, M>(a, g0, min((uint32_t)TPW, nblk - g0), lds, red, acc, rows, a, g0n, ntn, a.qs,
-                                     a.dqs);
+            process_group<TPW, S, M>(a, g0, min((uint32_t)TPW, nblk - g0), lds, red, acc, rows, a, g0n, ntn, qs,
+                                     dqs);
         }
     } else {
-        process_group<TPW, S, M>(a, g0, min((uint32_t)TPW, nblk - g0), lds, red, acc, rows, a, 0u, 0u, a.qs,
-                                 a.dqs);
+        process_group<TPW, S, M>(a, g0, min((uint32_t)TPW, nblk - g0), lds, red, acc, rows, a, 0u, 0u, qs, dqs);
     }
     if constexpr (M::SSE) {
         if (a.sse) sse_flush<TPW * 8>(acc, a.sse, red);
     }
+}
+
+template <int TPW, typename S, typename M, bool PF>
+__global__ __launch_bounds__(TPW * 8) void k_group(GroupArgs a, uint32_t nblk, uint32_t gpw, uint32_t spread_rows) {
+    __shared__ uint32_t lds[lds_words(TPW)];
+    __shared__ long long red[TPW * 8 / 64];
+    group_chunk<TPW, S, M, PF>(a, nblk, gpw, spread_rows, blockIdx.x, lds, red, a.qs, a.dqs);
+}
+
+// Several planes of one mode in one launch: plane i takes the workgroups
+// from first_wg (ascending) up to the next plane's, and runs them as
+// k_group would run its own launch over that plane alone.  Every plane of
+// the launch has the same quantiser (taken from plane 0).
+constexpr int kMaxPlanes = 8;
+struct PlaneLaunch {
+    GroupArgs a;
+    uint32_t nblk, gpw, spread_rows, first_wg;
+};
+struct PlaneSet {
+    PlaneLaunch p[kMaxPlanes];
+    uint32_t n;
+};
+
+template <int TPW, typename S, typename M, bool PF>
+__global__ __launch_bounds__(TPW * 8) void k_group_planes(PlaneSet ps) {
+    __shared__ uint32_t lds[lds_words(TPW)];
+    __shared__ long long red[TPW * 8 / 64];
+    uint32_t i = 0;
+#pragma unroll
+    for (uint32_t k = 1; k < (uint32_t)kMaxPlanes; ++k)
+        if (k < ps.n && blockIdx.x >= ps.p[k].first_wg) i = k;
+    const PlaneLaunch& pl = ps.p[i];
+    group_chunk<TPW, S, M, PF>(pl.a, pl.nblk, pl.gpw, pl.spread_rows, blockIdx.x - pl.first_wg, lds, red, ps.p[0].a.qs,
+                               ps.p[0].a.dqs);
 }
 
 #ifndef ADCT_TARGET_WGS

@@ -59,20 +59,31 @@ int check_recon(const adct_plane* dst, const adct_plane* ref, int32_t image_heig
     return ADCT_OK;
 }
 
+// Grid of a plain launch over nblk tiles: groups_per_wg groups per
+// workgroup; launches that add to the SSE of large images interleave their
+// chunks.
+struct GroupGrid {
+    uint32_t gpw, rows, grid;
+};
+GroupGrid group_grid(uint32_t nblk, bool sse, uint32_t image_tiles) {
+    GroupGrid g;
+    g.gpw = groups_per_wg(nblk);
+    const uint32_t span = g.gpw * (uint32_t)kTPW;
+    const uint32_t chunks = (nblk + span - 1) / span;
+    const bool spread = sse && image_tiles / span > kSseSpreadMin;
+    g.rows = spread ? (chunks + kSseSpread - 1) / kSseSpread : 0u;
+    g.grid = g.rows ? g.rows * kSseSpread : chunks;
+    return g;
+}
+
 template <typename S, typename M>
 int launch_group(uint32_t nblk, hipStream_t s, const GroupArgs& a) {
     if (nblk == 0) return ADCT_OK;
-    const uint32_t gpw = groups_per_wg(nblk);
-    const uint32_t span = gpw * (uint32_t)kTPW;
-    const uint32_t chunks = (nblk + span - 1) / span;
-    // launches that add to the SSE of large images interleave their chunks
-    const bool spread = M::SSE && a.sse && a.image_tiles / span > kSseSpreadMin;
-    const uint32_t rows = spread ? (chunks + kSseSpread - 1) / kSseSpread : 0u;
-    const uint32_t grid = rows ? rows * kSseSpread : chunks;
-    if (gpw == 1)
-        hipLaunchKernelGGL((k_group<kTPW, S, M, false>), dim3(grid), dim3(kTPW * 8), 0, s, a, nblk, gpw, rows);
+    const GroupGrid g = group_grid(nblk, M::SSE && a.sse, a.image_tiles);
+    if (g.gpw == 1)
+        hipLaunchKernelGGL((k_group<kTPW, S, M, false>), dim3(g.grid), dim3(kTPW * 8), 0, s, a, nblk, g.gpw, g.rows);
     else
-        hipLaunchKernelGGL((k_group<kTPW, S, M, true>), dim3(grid), dim3(kTPW * 8), 0, s, a, nblk, gpw, rows);
+        hipLaunchKernelGGL((k_group<kTPW, S, M, true>), dim3(g.grid), dim3(kTPW * 8), 0, s, a, nblk, g.gpw, g.rows);
     return launched();
 }
 
@@ -108,20 +119,44 @@ int launch_zonal(int32_t dtype, int r, uint32_t nblk, hipStream_t s, const Group
     return launch_group<int16_t, Mode<IN, STORE, kMidZonal, kOutSamples, -1, SSE>>(nblk, s, a);
 }
 
-// Clears the per-image SSE accumulators (a fill kernel, so that the call can
-// be captured in a graph) and fills the SSE fields of `a`.
-int prepare_sse(const adct_plane* dst, const adct_plane* ref, int32_t image_height, int64_t* sse,
-                hipStream_t s, GroupArgs& a) {
+// Fills the SSE fields of `a` (no launch).
+void sse_fields(const adct_plane* dst, const adct_plane* ref, int32_t image_height, int64_t* sse, GroupArgs& a) {
     a.ipbdiv = make_fastdiv(1);
-    if (!sse) return ADCT_OK;
-    const uint32_t nimg = (uint32_t)(dst->height / image_height);
-    hipLaunchKernelGGL(k_zero_u64, dim3((nimg + 255) / 256), dim3(256), 0, s,
-                       reinterpret_cast<unsigned long long*>(sse), nimg);
+    if (!sse) return;
     a.ref = plane_ref(ref ? ref : dst);
     a.ipbdiv = make_fastdiv((uint32_t)(image_height / 16));
     a.image_tiles = (uint32_t)(image_height / 16) * (uint32_t)(dst->width / 16);
     a.sse = reinterpret_cast<unsigned long long*>(sse);
+}
+
+// Clears the per-image SSE accumulators (a fill kernel, so that the call can
+// be captured in a graph) and fills the SSE fields of `a`.
+int prepare_sse(const adct_plane* dst, const adct_plane* ref, int32_t image_height, int64_t* sse,
+                hipStream_t s, GroupArgs& a) {
+    sse_fields(dst, ref, image_height, sse, a);
+    if (!sse) return ADCT_OK;
+    const uint32_t nimg = (uint32_t)(dst->height / image_height);
+    hipLaunchKernelGGL(k_zero_u64, dim3((nimg + 255) / 256), dim3(256), 0, s,
+                       reinterpret_cast<unsigned long long*>(sse), nimg);
     return launched();
+}
+
+template <typename S, typename M>
+int launch_planes(const PlaneSet& ps, uint32_t grid, bool pf, hipStream_t s) {
+    if (pf)
+        hipLaunchKernelGGL((k_group_planes<kTPW, S, M, true>), dim3(grid), dim3(kTPW * 8), 0, s, ps);
+    else
+        hipLaunchKernelGGL((k_group_planes<kTPW, S, M, false>), dim3(grid), dim3(kTPW * 8), 0, s, ps);
+    return launched();
+}
+
+template <int STORE, bool SSE>
+int launch_quant_planes(int32_t dtype, bool fit, const PlaneSet& ps, uint32_t grid, bool pf, hipStream_t s) {
+    if (dtype == ADCT_U8)
+        return launch_planes<uint8_t, Mode<kInSamples, STORE, kMidQuant, kOutSamples, -1, SSE>>(ps, grid, pf, s);
+    if (fit)
+        return launch_planes<int16_t, Mode<kInSamples, STORE, kMidQuantFit, kOutSamples, -1, SSE>>(ps, grid, pf, s);
+    return launch_planes<int16_t, Mode<kInSamples, STORE, kMidQuant, kOutSamples, -1, SSE>>(ps, grid, pf, s);
 }
 
 }  // namespace
@@ -418,6 +453,69 @@ int adct_encode_quant(const adct_plane* src, int qp, int16_t* q, const adct_plan
                    : launch_quant<kStoreQ, kOutSamples, false>(dt, fit, n, s, a);
     return sse ? launch_quant<kStoreNone, kOutSamples, true>(dt, fit, n, s, a)
                : launch_quant<kStoreNone, kOutSamples, false>(dt, fit, n, s, a);
+}
+
+int adct_encode_quant_planes(const adct_quant_job* jobs, int32_t njobs, int qp, void* stream) {
+    Scale5Host qs, dqs;
+    if (!quant_scales(qp, &qs, &dqs)) return ADCT_E_ARG;
+    if (!jobs || njobs < 1 || njobs > ADCT_MAX_PLANES) return ADCT_E_ARG;
+    static_assert(ADCT_MAX_PLANES <= kMaxPlanes && ADCT_MAX_PLANES <= kMaxZero, "one launch holds every plane");
+    const bool store = jobs[0].q != nullptr, want_sse = jobs[0].sse != nullptr;
+    const int32_t dt = jobs[0].src.dtype;
+    PlaneSet ps{};
+    ZeroSet zs{};
+    uint64_t grid = 0;
+    uint32_t max_img = 0;
+    bool pf = false;
+    for (int32_t i = 0; i < njobs; ++i) {
+        const adct_quant_job& j = jobs[i];
+        int rc = check_plane(&j.src);
+        if (rc) return rc;
+        if ((rc = check_plane(&j.dst))) return rc;
+        if (!same_shape(&j.src, &j.dst)) return ADCT_E_SHAPE;
+        if (j.src.dtype != dt || (j.q != nullptr) != store || (j.sse != nullptr) != want_sse) return ADCT_E_ARG;
+        if (want_sse) {
+            if (j.image_height <= 0 || (j.image_height & 15) || j.src.height % j.image_height) return ADCT_E_SHAPE;
+            if ((uintptr_t)j.sse & 7) return ADCT_E_ALIGN;
+        }
+        const int64_t nblk = plane_blocks(&j.src);
+        if (store && (rc = check_blocks(j.q, nblk))) return rc;
+        PlaneLaunch& pl = ps.p[i];
+        GroupArgs& a = pl.a;
+        a.src = plane_ref(&j.src);
+        set_geometry(&j.src, a);
+        a.dst = plane_ref(&j.dst);
+        a.cout = j.q;
+        a.qs = to_dev(qs);
+        a.dqs = to_dev(dqs);
+        sse_fields(&j.dst, &j.src, j.image_height, j.sse, a);
+        const GroupGrid g = group_grid((uint32_t)nblk, want_sse, a.image_tiles);
+        pl.nblk = (uint32_t)nblk;
+        pl.gpw = g.gpw;
+        pl.spread_rows = g.rows;
+        pl.first_wg = (uint32_t)grid;
+        grid += g.grid;
+        pf = pf || g.gpw > 1;
+        if (want_sse) {
+            zs.p[i] = reinterpret_cast<unsigned long long*>(j.sse);
+            zs.n[i] = (uint32_t)(j.src.height / j.image_height);
+            max_img = std::max(max_img, zs.n[i]);
+        }
+    }
+    if (grid > (uint64_t)INT32_MAX) return ADCT_E_TOO_LARGE;
+    ps.n = (uint32_t)njobs;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (want_sse) {
+        zs.count = (uint32_t)njobs;
+        hipLaunchKernelGGL(k_zero_sets, dim3((max_img + 255) / 256, (unsigned)njobs), dim3(256), 0, s, zs);
+        if (int rc = launched()) return rc;
+    }
+    const bool fit = i16_levels_fit(qs);
+    if (store)
+        return want_sse ? launch_quant_planes<kStoreQ, true>(dt, fit, ps, (uint32_t)grid, pf, s)
+                        : launch_quant_planes<kStoreQ, false>(dt, fit, ps, (uint32_t)grid, pf, s);
+    return want_sse ? launch_quant_planes<kStoreNone, true>(dt, fit, ps, (uint32_t)grid, pf, s)
+                    : launch_quant_planes<kStoreNone, false>(dt, fit, ps, (uint32_t)grid, pf, s);
 }
 
 int adct_sse(const adct_plane* a, const adct_plane* b, int32_t image_height, int64_t* sse, void* stream) {
