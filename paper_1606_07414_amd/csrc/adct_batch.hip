@@ -72,13 +72,13 @@ __global__ __launch_bounds__(TPW * 8) void k_batch(BatchArgs b, const GroupArgs*
     if (!claim_item(b, home, qi, q, c, &sh_claim)) return;
     ItemDev item = items[b.qbeg[q] + c];
     RowWords rows;
-    load_group_rows<TPW, S>(jobs[item.job], item.first, min((uint32_t)TPW, item.count), rows);
+    load_group_rows<TPW, S>(global_args(jobs[item.job]), item.first, min((uint32_t)TPW, item.count), rows);
     for (;;) {
         // claim the next item of this sub-queue now; the atomic's latency
         // overlaps this item's groups
         uint32_t next = 0;
         if (tid == 0) next = atomicAdd(b.heads + q * kHeadStride, 1u);
-        const GroupArgs a = jobs[item.job];
+        const GroupArgs a = global_args(jobs[item.job]);
         const uint32_t gend = item.first + item.count;
         SseAcc acc{0, kNoImage};
         bool have_next = false;
@@ -106,8 +106,8 @@ __global__ __launch_bounds__(TPW * 8) void k_batch(BatchArgs b, const GroupArgs*
             }
             // (the scale tables are read from the job array itself: indexed
             // reads of a private copy would go through scratch)
-            process_group<TPW, S, M>(a, g0, min((uint32_t)TPW, gend - g0), lds, red, acc, rows, jobs[nitem.job],
-                                     g0n, ntn, jobs[item.job].qs, jobs[item.job].dqs);
+            process_group<TPW, S, M>(a, g0, min((uint32_t)TPW, gend - g0), lds, red, acc, rows,
+                                     global_args(jobs[nitem.job]), g0n, ntn, jobs[item.job].qs, jobs[item.job].dqs);
         }
         if (a.sse) sse_flush<TPW * 8>(acc, a.sse, red);
         if (have_next) {
@@ -120,7 +120,7 @@ __global__ __launch_bounds__(TPW * 8) void k_batch(BatchArgs b, const GroupArgs*
         if (!claim_item(b, home, qi, q, c, &sh_claim)) break;
         item = items[b.qbeg[q] + c];
         __syncthreads();  // every thread is finished with LDS (sse_flush, last group)
-        load_group_rows<TPW, S>(jobs[item.job], item.first, min((uint32_t)TPW, item.count), rows);
+        load_group_rows<TPW, S>(global_args(jobs[item.job]), item.first, min((uint32_t)TPW, item.count), rows);
     }
 }
 
@@ -129,7 +129,7 @@ __global__ __launch_bounds__(TPW * 8) void k_batch(BatchArgs b, const GroupArgs*
 __global__ __launch_bounds__(256) void k_batch_reset(uint32_t* heads, const GroupArgs* jobs, uint32_t njobs) {
     const uint32_t t = blockIdx.x * 256u + threadIdx.x;
     if (t < kQueues) heads[t * kHeadStride] = 0u;
-    if (t < njobs && jobs[t].sse) *jobs[t].sse = 0ull;
+    if (t < njobs && jobs[t].sse) *as_global(jobs[t].sse) = 0ull;
 }
 
 namespace {

@@ -90,6 +90,30 @@ struct GroupArgs {
     uint32_t image_tiles;    // tiles per image (launch geometry only)
 };
 
+// A device address as a pointer the compiler knows to be in global memory.
+// Pointers read from memory (a job table, rather than kernel arguments) are
+// generic to it, and it would access them with flat instructions; flat
+// memory operations also count against the counter that LDS and scalar
+// loads wait on, so every wait of an LDS transpose would then wait for the
+// outstanding HBM traffic as well.
+template <typename T>
+__device__ __forceinline__ T* as_global(T* p) {
+    typedef __attribute__((address_space(1))) T gT;
+    return (T*)(gT*)(uintptr_t)p;
+}
+
+// GroupArgs read from memory, with every pointer marked global.
+__device__ __forceinline__ GroupArgs global_args(GroupArgs a) {
+    a.src.data = as_global(a.src.data);
+    a.dst.data = as_global(a.dst.data);
+    a.ref.data = as_global(a.ref.data);
+    a.cin = as_global(a.cin);
+    a.cout = as_global(a.cout);
+    a.bout = as_global(a.bout);
+    a.sse = as_global(a.sse);
+    return a;
+}
+
 // ---- sample rows as 16-bit pairs ------------------------------------------------
 // Rows ip and ip+8 of a tile, raw words (uint8: 16 samples in a0; int16: 8
 // samples each in a0, a1; likewise b for row ip+8), as 16 packed pairs
