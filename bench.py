@@ -206,7 +206,8 @@ def video(torch, adct, stream, frames=64):
     single-pass encoder (levels + reconstruction + per-frame SSE) over all
     three planes in one launch, the same per plane (three launches), and the
     two-kernel path; the same frames coded with the 8-point transform on 8x8
-    blocks; and with mixed 8/16-point coding."""
+    blocks and the 32-point one on 32x32 blocks (each in one launch, and per
+    plane); and with mixed 8/16-point coding."""
     import synth
     planes = [[], [], []]
     for f in range(frames):
@@ -250,15 +251,19 @@ def video(torch, adct, stream, frames=64):
         # the same frames with the 8-point transform on 8x8 blocks (Section 3.2's
         # second scenario codes with both sizes): levels, reconstruction, SSE
         def fused8():
+            adct.encode_quant_planes(list(zip(xs, outs, q8s, heights, sses)), qp, block=8, stream=stream)
+
+        def fused8_per_plane():
             for x, o, q8, s, h in zip(xs, outs, q8s, sses, heights):
                 adct.t8_encode_quant(x, qp, o, q=q8, image_height=h, sse=s, stream=stream)
 
         ms8 = timed(torch, fused8, 10, stream)
+        ms8p = timed(torch, fused8_per_plane, 10, stream)
         fused8()
         sse8 = [s.cpu().numpy().astype(np.float64) for s in sses]
         psnr8 = [10 * np.log10(255.0 ** 2 * n / np.maximum(e, 1)) for e, n in zip(sse8, npix)]
         res["qp"][qp]["t8"] = {"ms": ms8, "blocks8_per_s": 4 * tiles / (ms8 * 1e-3),
-                               "gbs": 384 * 4 * tiles / (ms8 * 1e-3) / 1e9,
+                               "gbs": 384 * 4 * tiles / (ms8 * 1e-3) / 1e9, "per_plane_ms": ms8p,
                                "psnr_yuv_6_1_1_db": float(np.mean((6 * psnr8[0] + psnr8[1] + psnr8[2]) / 8))}
         # mixed 8/16-point coding (the second scenario with both transforms):
         # per 16x16 region the coding of lower D + lambda R, lambda the usual
@@ -286,14 +291,18 @@ def video(torch, adct, stream, frames=64):
     q32s = [torch.empty((x.numel() // 1024, 32, 32), dtype=torch.int16, device="cuda") for x in xs]
     for qp in (22, 27, 32, 37):
         def fused32():
+            adct.encode_quant_planes(list(zip(xs, outs, q32s, heights, sses)), qp, block=32, stream=stream)
+
+        def fused32_per_plane():
             for x, o, q, s, h in zip(xs, outs, q32s, sses, heights):
                 adct.t32_encode_quant(x, qp, o, q=q, image_height=h, sse=s, stream=stream)
 
         ms32 = timed(torch, fused32, 10, stream)
+        ms32p = timed(torch, fused32_per_plane, 10, stream)
         fused32()
         sse32 = [s.cpu().numpy().astype(np.float64) for s in sses]
         psnr32 = [10 * np.log10(255.0 ** 2 * n / np.maximum(e, 1)) for e, n in zip(sse32, npix)]
-        res["qp"][qp]["t32"] = {"ms": ms32, "blocks32_per_s": tiles / 4 / (ms32 * 1e-3),
+        res["qp"][qp]["t32"] = {"ms": ms32, "per_plane_ms": ms32p, "blocks32_per_s": tiles / 4 / (ms32 * 1e-3),
                                 "gbs": 6144 * (tiles / 4) / (ms32 * 1e-3) / 1e9,
                                 "psnr_yuv_6_1_1_db": float(np.mean((6 * psnr32[0] + psnr32[1] + psnr32[2]) / 8))}
     res["additions_per_sample_2d"] = {"t16": 2 * 44 / 16, "t8": 2 * 14 / 8, "t32": 2 * 120 / 32}
@@ -538,6 +547,8 @@ def summary_line(full: dict) -> dict:
         if v:
             summ["video_fused_ms_per_qp"] = {str(q): round(r["fused_ms"], 4) for q, r in v["qp"].items()}
             summ["video_fused_frac"] = {str(q): round(r["fused_gbs"] / HBM_PEAK_GBS, 3) for q, r in v["qp"].items()}
+            summ["video_t8_t32_ms_per_qp"] = {str(q): [round(r[k]["ms"], 4) if k in r else None for k in ("t8", "t32")]
+                                              for q, r in v["qp"].items()}
         b = other.get("uneven_batch_4096")
         if b:
             summ["uneven_batch"] = {"tiles": b["tiles"], "zonal_r8_ms": round(b["ms"], 3),

@@ -248,26 +248,31 @@ int adct_encode_zigzag(const adct_plane* src, int r, int32_t* coef, const adct_p
 int adct_encode_quant(const adct_plane* src, int qp, int16_t* q, const adct_plane* dst,
                       int32_t image_height, int64_t* sse, void* stream);
 
-/* adct_encode_quant over several planes at one QP in one launch (with one
- * clear of every SSE output before it): the planes of a video frame stack
- * (Y, U and V, which differ in size), or any other set.  Each job is coded
- * exactly as adct_encode_quant would code it alone (bit-identical levels,
- * reconstruction and SSE); the short launches of small planes no longer
- * each fill and drain the device on their own.  All jobs must have the same
- * dtype, and either all or none of them store levels (q) and SSE.
+/* Quantising single-pass encoders over several planes at one QP in one
+ * launch (with one clear of every SSE output before it): the planes of a
+ * video frame stack (Y, U and V, which differ in size), or any other set.
+ * block selects the transform and block size:
+ *   16  T on 16x16 blocks, each job coded exactly as adct_encode_quant;
+ *    8  T8 on 8x8 blocks, as adct_t8_encode_quant;
+ *   32  T32 on 32x32 blocks, as adct_t32_encode_quant;
+ * with that call's plane rules, level layout ([blocks][block][block], block
+ * rows in raster order) and image heights (multiples of block).  Results are
+ * bit-identical to the per-plane call; the short launches of small planes
+ * no longer each fill and drain the device on their own.  All jobs must have
+ * the same dtype, and either all or none of them store levels (q) and SSE.
  * njobs in [1, ADCT_MAX_PLANES].  Jobs must not overlap in their outputs. */
 #define ADCT_MAX_PLANES 8
 
 typedef struct adct_quant_job {
     adct_plane src;          /* samples in                                      */
     adct_plane dst;          /* reconstruction out, same shape and type as src  */
-    int16_t* q;              /* levels out, block-major [tiles][16][16], or NULL */
+    int16_t* q;              /* levels out, block-major, or NULL                */
     int64_t* sse;            /* per-image SSE [src.height / image_height], or NULL */
     int32_t image_height;    /* rows per image when sse is set                  */
     int32_t reserved;
 } adct_quant_job;
 
-int adct_encode_quant_planes(const adct_quant_job* jobs, int32_t njobs, int qp, void* stream);
+int adct_encode_quant_planes(const adct_quant_job* jobs, int32_t njobs, int qp, int32_t block, void* stream);
 
 /* ---- comparison transforms through the same codec ----------------------- */
 /* Tables 1 and 2 compare the approximation with the exact DCT and with the

@@ -132,7 +132,7 @@ _SIGNATURES = {
     "adct_dequant_recon": (ctypes.c_int, [_P, ctypes.c_int, _PP, _PP, _I32, _P, _P]),
     "adct_encode_zonal": (ctypes.c_int, [_PP, ctypes.c_int, _P, _PP, _I32, _P, _P]),
     "adct_encode_quant": (ctypes.c_int, [_PP, ctypes.c_int, _P, _PP, _I32, _P, _P]),
-    "adct_encode_quant_planes": (ctypes.c_int, [_P, _I32, ctypes.c_int, _P]),
+    "adct_encode_quant_planes": (ctypes.c_int, [_P, _I32, ctypes.c_int, _I32, _P]),
     "adct_default_tune": (ctypes.c_int, [ctypes.POINTER(Tune)]),
     "adct_work_queue": (ctypes.c_int, [_P, _I32, _I32, _I32, _P, _I64, ctypes.POINTER(_I64)]),
     "adct_batch_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.POINTER(Job), _I32, _I32, _I32,
@@ -634,11 +634,12 @@ def encode_quant(src, qp: int, dst, q=None, image_height=None, sse=None, want_ss
     return sse
 
 
-def encode_quant_planes(jobs, qp: int, want_sse=True, stream=None):
-    """adct_encode_quant over several planes in one launch.  jobs: a list of
-    (src, dst, q, image_height, sse) with q, image_height and sse optional
-    (q None for all jobs or for none; sse allocated when None and want_sse).
-    Returns the list of per-image SSE tensors (None entries when not wanted)."""
+def encode_quant_planes(jobs, qp: int, block: int = 16, want_sse=True, stream=None):
+    """Quantising encoder (block 16: T, 8: T8 on 8x8, 32: T32 on 32x32) over
+    several planes in one launch.  jobs: a list of (src, dst, q,
+    image_height, sse) with q, image_height and sse optional (q None for all
+    jobs or for none; sse allocated when None and want_sse).  Returns the
+    list of per-image SSE tensors (None entries when not wanted)."""
     arr = (QuantJob * max(1, len(jobs)))()
     keep, out = [], []
     for i, job in enumerate(jobs):
@@ -650,7 +651,7 @@ def encode_quant_planes(jobs, qp: int, want_sse=True, stream=None):
         arr[i] = QuantJob(plane(src), plane(dst), q.data_ptr() if q is not None else None, sp, ih, 0)
         keep.append((src, dst, q, sse_t))
         out.append(sse_t)
-    _check(_lib().adct_encode_quant_planes(arr, len(jobs), qp, _stream(stream)), "encode_quant_planes")
+    _check(_lib().adct_encode_quant_planes(arr, len(jobs), qp, block, _stream(stream)), "encode_quant_planes")
     return out
 
 

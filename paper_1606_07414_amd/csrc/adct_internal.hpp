@@ -28,6 +28,12 @@ int class_of(int u, int v);
 int launch_dct_codec(const adct_plane* src, int32_t kind, int r, const adct_plane* dst, int32_t image_height,
                      int64_t* sse, void* stream);
 
+// adct_encode_quant_planes for 8x8 blocks with T8 (adct_t8.hip) and 32x32
+// blocks with T32 (adct_t32.hip); njobs already checked against
+// ADCT_MAX_PLANES.
+int t8_encode_quant_planes(const adct_quant_job* jobs, int32_t njobs, int qp, void* stream);
+int t32_encode_quant_planes(const adct_quant_job* jobs, int32_t njobs, int qp, void* stream);
+
 inline int sample_bytes(int32_t dtype) { return dtype == ADCT_U8 ? 1 : dtype == ADCT_I16 ? 2 : 0; }
 
 // Validate a plane descriptor (see the conventions in adct.h).

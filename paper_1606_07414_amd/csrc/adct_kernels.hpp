@@ -141,18 +141,4 @@ __global__ __launch_bounds__(256) void k_zero_u64(unsigned long long* p, uint32_
     if (t < n) p[t] = 0ull;
 }
 
-// Clears up to kMaxZero arrays in one launch: row y of the grid clears
-// array y (arrays of n[y] == 0 or past `count` are skipped).
-constexpr int kMaxZero = 8;
-struct ZeroSet {
-    unsigned long long* p[kMaxZero];
-    uint32_t n[kMaxZero];
-    uint32_t count;
-};
-
-__global__ __launch_bounds__(256) void k_zero_sets(ZeroSet z) {
-    const uint32_t y = blockIdx.y, t = blockIdx.x * 256u + threadIdx.x;
-    if (y < z.count && t < z.n[y]) z.p[y][t] = 0ull;
-}
-
 }  // namespace adct

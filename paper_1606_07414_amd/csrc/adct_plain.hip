@@ -8,6 +8,7 @@
 #include "adct_internal.hpp"
 #include "adct_core.hpp"
 #include "adct_kernels.hpp"
+#include "adct_zero.hpp"
 
 namespace adct {
 namespace {
@@ -455,17 +456,20 @@ int adct_encode_quant(const adct_plane* src, int qp, int16_t* q, const adct_plan
                : launch_quant<kStoreNone, kOutSamples, false>(dt, fit, n, s, a);
 }
 
-int adct_encode_quant_planes(const adct_quant_job* jobs, int32_t njobs, int qp, void* stream) {
+int adct_encode_quant_planes(const adct_quant_job* jobs, int32_t njobs, int qp, int32_t block, void* stream) {
+    if (!jobs || njobs < 1 || njobs > ADCT_MAX_PLANES) return ADCT_E_ARG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (block == 8) return t8_encode_quant_planes(jobs, njobs, qp, stream);
+    if (block == 32) return t32_encode_quant_planes(jobs, njobs, qp, stream);
+    if (block != 16) return ADCT_E_ARG;
     Scale5Host qs, dqs;
     if (!quant_scales(qp, &qs, &dqs)) return ADCT_E_ARG;
-    if (!jobs || njobs < 1 || njobs > ADCT_MAX_PLANES) return ADCT_E_ARG;
-    static_assert(ADCT_MAX_PLANES <= kMaxPlanes && ADCT_MAX_PLANES <= kMaxZero, "one launch holds every plane");
+    static_assert(ADCT_MAX_PLANES <= kMaxPlanes, "one launch holds every plane");
     const bool store = jobs[0].q != nullptr, want_sse = jobs[0].sse != nullptr;
     const int32_t dt = jobs[0].src.dtype;
     PlaneSet ps{};
-    ZeroSet zs{};
+    ZeroSet<ADCT_MAX_PLANES> zs{};
     uint64_t grid = 0;
-    uint32_t max_img = 0;
     bool pf = false;
     for (int32_t i = 0; i < njobs; ++i) {
         const adct_quant_job& j = jobs[i];
@@ -499,15 +503,13 @@ int adct_encode_quant_planes(const adct_quant_job* jobs, int32_t njobs, int qp, 
         if (want_sse) {
             zs.p[i] = reinterpret_cast<unsigned long long*>(j.sse);
             zs.n[i] = (uint32_t)(j.src.height / j.image_height);
-            max_img = std::max(max_img, zs.n[i]);
         }
     }
     if (grid > (uint64_t)INT32_MAX) return ADCT_E_TOO_LARGE;
     ps.n = (uint32_t)njobs;
-    hipStream_t s = static_cast<hipStream_t>(stream);
     if (want_sse) {
         zs.count = (uint32_t)njobs;
-        hipLaunchKernelGGL(k_zero_sets, dim3((max_img + 255) / 256, (unsigned)njobs), dim3(256), 0, s, zs);
+        clear_sets(zs, s);
         if (int rc = launched()) return rc;
     }
     const bool fit = i16_levels_fit(qs);

@@ -26,6 +26,7 @@
 #include "adct_round.hpp"
 #include "adct_t32_common.hpp"
 #include "adct_tile.hpp"
+#include "adct_zero.hpp"
 
 namespace adct {
 namespace {
@@ -139,13 +140,13 @@ __device__ __forceinline__ void column_factors32(const Scale5& t, int v, float (
     for (int l = 3; l <= 5; ++l) out[l - 3] = pick5(t, l + lv - 6);
 }
 
+// Workgroup b of a launch over the plane of `a` (256 threads).
 template <typename S, int OP, bool STORE, bool SSE>
-__global__ __launch_bounds__(256) void k_t32(Args32 a) {
+__device__ __forceinline__ void t32_group(const Args32& a, uint32_t b) {
     __shared__ __align__(16) int32_t lds[kTiles32 * kTile32];
     __shared__ long long red[4];
     const int tid = threadIdx.x;
-    const uint32_t group =
-        a.spread_rows ? (blockIdx.x % kSpread32) * a.spread_rows + blockIdx.x / kSpread32 : blockIdx.x;
+    const uint32_t group = a.spread_rows ? (b % kSpread32) * a.spread_rows + b / kSpread32 : b;
     const uint32_t g0 = group * (uint32_t)kTiles32;
     if (g0 >= a.nblk) return;  // past the last group (interleaved grids only)
     const uint32_t ntile = min((uint32_t)kTiles32, a.nblk - g0);
@@ -269,6 +270,28 @@ __global__ __launch_bounds__(256) void k_t32(Args32 a) {
 constexpr int kInvRow = 36;                     // output staging: words per row
 constexpr int kInvTile = 32 * kInvRow + 4;      // and per tile
 
+template <typename S, int OP, bool STORE, bool SSE>
+__global__ __launch_bounds__(256) void k_t32(Args32 a) {
+    t32_group<S, OP, STORE, SSE>(a, blockIdx.x);
+}
+
+// Several planes in one launch: plane i takes the workgroups from first[i]
+// (ascending) up to the next plane's, as k_t32 would over that plane alone.
+struct Set32 {
+    Args32 p[ADCT_MAX_PLANES];
+    uint32_t first[ADCT_MAX_PLANES];
+    uint32_t n;
+};
+
+template <typename S, int OP, bool STORE, bool SSE>
+__global__ __launch_bounds__(256) void k_t32_planes(Set32 ps) {
+    uint32_t i = 0;
+#pragma unroll
+    for (uint32_t k = 1; k < (uint32_t)ADCT_MAX_PLANES; ++k)
+        if (k < ps.n && blockIdx.x >= ps.first[k]) i = k;
+    t32_group<S, OP, STORE, SSE>(ps.p[i], blockIdx.x - ps.first[i]);
+}
+
 __global__ __launch_bounds__(256) void k_t32_inv(const int32_t* __restrict__ in, int32_t* __restrict__ out,
                                                 uint32_t nblk) {
     __shared__ __align__(16) int32_t out_stage[kTiles32 * kInvTile];
@@ -332,9 +355,13 @@ int check_plane32(const adct_plane* p) {
 
 int64_t blocks32(const adct_plane* p) { return (int64_t)(p->height / 32) * (p->width / 32); }
 
+uint32_t grid32(const Args32& a) {
+    return a.spread_rows ? a.spread_rows * kSpread32 : (a.nblk + kTiles32 - 1) / kTiles32;
+}
+
 template <typename S, int OP, bool STORE>
 void launch32(const Args32& a, hipStream_t s) {
-    const dim3 grid(a.spread_rows ? a.spread_rows * kSpread32 : (a.nblk + kTiles32 - 1) / kTiles32);
+    const dim3 grid(grid32(a));
     if (a.sse)
         hipLaunchKernelGGL((k_t32<S, OP, STORE, true>), grid, dim3(256), 0, s, a);
     else
@@ -352,10 +379,10 @@ int launch32_typed(int32_t dtype, const Args32& a, hipStream_t s) {
     return launched();
 }
 
-// Shared checks and set-up of the encoders (and the forward call, with no
-// destination).
-int setup32(const adct_plane* src, void* coef, const adct_plane* dst, int32_t image_height, int64_t* sse,
-            hipStream_t s, Args32& a) {
+// Shared checks and argument set-up of the encoders (and the forward call,
+// with no destination); no launch.
+int setup_args32(const adct_plane* src, void* coef, const adct_plane* dst, int32_t image_height, int64_t* sse,
+                 Args32& a) {
     int rc = check_plane32(src);
     if (rc) return rc;
     if (dst) {
@@ -381,14 +408,75 @@ int setup32(const adct_plane* src, void* coef, const adct_plane* dst, int32_t im
         const uint32_t groups = (a.nblk + kTiles32 - 1) / kTiles32;
         const uint32_t image_tiles = (uint32_t)(image_height / 32) * a.bw;
         if (image_tiles / kTiles32 > kSpreadMin32) a.spread_rows = (groups + kSpread32 - 1) / kSpread32;
-        const uint32_t nimg = (uint32_t)(src->height / image_height);
-        hipLaunchKernelGGL(k_t32_zero, dim3((nimg + 255) / 256), dim3(256), 0, s, a.sse, nimg);
-        return launched();
     }
     return ADCT_OK;
 }
 
+// The same, then the clear of the SSE output.
+int setup32(const adct_plane* src, void* coef, const adct_plane* dst, int32_t image_height, int64_t* sse,
+            hipStream_t s, Args32& a) {
+    const int rc = setup_args32(src, coef, dst, image_height, sse, a);
+    if (rc || !sse) return rc;
+    const uint32_t nimg = (uint32_t)(src->height / image_height);
+    hipLaunchKernelGGL(k_t32_zero, dim3((nimg + 255) / 256), dim3(256), 0, s, a.sse, nimg);
+    return launched();
+}
+
+template <typename S, bool STORE, bool SSE>
+void launch32_planes(const Set32& ps, uint32_t grid, hipStream_t s) {
+    hipLaunchKernelGGL((k_t32_planes<S, kQuant32, STORE, SSE>), dim3(grid), dim3(256), 0, s, ps);
+}
+
+template <typename S>
+void launch32_planes_typed(const Set32& ps, uint32_t grid, bool store, bool sse, hipStream_t s) {
+    if (store) {
+        if (sse) launch32_planes<S, true, true>(ps, grid, s); else launch32_planes<S, true, false>(ps, grid, s);
+    } else {
+        if (sse) launch32_planes<S, false, true>(ps, grid, s); else launch32_planes<S, false, false>(ps, grid, s);
+    }
+}
+
 }  // namespace
+
+int t32_encode_quant_planes(const adct_quant_job* jobs, int32_t njobs, int qp, void* stream) {
+    float qs[5], dqs[5];
+    if (!quant_scales32(qp, qs, dqs)) return ADCT_E_ARG;
+    const bool store = jobs[0].q != nullptr, want_sse = jobs[0].sse != nullptr;
+    const int32_t dt = jobs[0].src.dtype;
+    Set32 ps{};
+    ZeroSet<ADCT_MAX_PLANES> zs{};
+    uint64_t grid = 0;
+    for (int32_t i = 0; i < njobs; ++i) {
+        const adct_quant_job& j = jobs[i];
+        if (j.src.dtype != dt || (j.q != nullptr) != store || (j.sse != nullptr) != want_sse) return ADCT_E_ARG;
+        Args32& a = ps.p[i];
+        const int rc = setup_args32(&j.src, j.q, &j.dst, j.image_height, j.sse, a);
+        if (rc) return rc;
+        for (int c = 0; c < 5; ++c) {
+            a.qs.f[c] = qs[c];
+            a.dqs.f[c] = dqs[c];
+        }
+        ps.first[i] = (uint32_t)grid;
+        grid += grid32(a);
+        if (want_sse) {
+            zs.p[i] = a.sse;
+            zs.n[i] = (uint32_t)(j.src.height / j.image_height);
+        }
+    }
+    if (grid > (uint64_t)INT32_MAX) return ADCT_E_TOO_LARGE;
+    ps.n = (uint32_t)njobs;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (want_sse) {
+        zs.count = (uint32_t)njobs;
+        clear_sets(zs, s);
+    }
+    if (dt == ADCT_U8)
+        launch32_planes_typed<uint8_t>(ps, (uint32_t)grid, store, want_sse, s);
+    else
+        launch32_planes_typed<int16_t>(ps, (uint32_t)grid, store, want_sse, s);
+    return launched();
+}
+
 }  // namespace adct
 
 using namespace adct;

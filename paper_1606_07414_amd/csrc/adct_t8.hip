@@ -21,6 +21,7 @@
 #include "adct_internal.hpp"
 #include "adct_t8_common.hpp"
 #include "adct_tile.hpp"
+#include "adct_zero.hpp"
 
 namespace adct {
 namespace {
@@ -131,8 +132,9 @@ __device__ __forceinline__ void wave_store_half(uint32_t* lds, const uint32_t (&
     }
 }
 
+// Workgroup b of a launch over the plane of `a` (256 threads).
 template <typename S, int OP, bool STORE, bool SSE>
-__global__ __launch_bounds__(256) void k_t8(Args8 a) {
+__device__ __forceinline__ void t8_chunk(const Args8& a, uint32_t b) {
     constexpr int kHalf = OP == kQuant8 ? 16 : 32;  // 32-bit words of half a stored block
     __shared__ uint32_t lds[4][64 * (kHalf + 1)];
     __shared__ long long red[2][4];
@@ -141,8 +143,7 @@ __global__ __launch_bounds__(256) void k_t8(Args8 a) {
     constexpr int kRowWords = sizeof(S) == 1 ? 2 : 4;
     __shared__ uint32_t src_rows[SSE ? 8 : 1][SSE ? 256 * kRowWords : 1];
     // chunk of 256 consecutive blocks taken by this workgroup
-    const uint32_t chunk =
-        a.spread_rows ? (blockIdx.x % kSpread8) * a.spread_rows + blockIdx.x / kSpread8 : blockIdx.x;
+    const uint32_t chunk = a.spread_rows ? (b % kSpread8) * a.spread_rows + b / kSpread8 : b;
     const uint32_t first = chunk * 256u;
     if (first >= a.nblk) return;  // past the last chunk (spread grids only)
     const uint32_t g = first + threadIdx.x;
@@ -299,6 +300,28 @@ __global__ __launch_bounds__(256) void k_t8(Args8 a) {
     }
 }
 
+template <typename S, int OP, bool STORE, bool SSE>
+__global__ __launch_bounds__(256) void k_t8(Args8 a) {
+    t8_chunk<S, OP, STORE, SSE>(a, blockIdx.x);
+}
+
+// Several planes in one launch: plane i takes the workgroups from first[i]
+// (ascending) up to the next plane's, as k_t8 would over that plane alone.
+struct Set8 {
+    Args8 p[ADCT_MAX_PLANES];
+    uint32_t first[ADCT_MAX_PLANES];
+    uint32_t n;
+};
+
+template <typename S, int OP, bool STORE, bool SSE>
+__global__ __launch_bounds__(256) void k_t8_planes(Set8 ps) {
+    uint32_t i = 0;
+#pragma unroll
+    for (uint32_t k = 1; k < (uint32_t)ADCT_MAX_PLANES; ++k)
+        if (k < ps.n && blockIdx.x >= ps.first[k]) i = k;
+    t8_chunk<S, OP, STORE, SSE>(ps.p[i], blockIdx.x - ps.first[i]);
+}
+
 // T8^T Y T8 per block (block-major int32 in and out).
 __global__ __launch_bounds__(256) void k_t8_inv(const int32_t* __restrict__ in, int32_t* __restrict__ out,
                                                uint32_t nblk) {
@@ -356,9 +379,11 @@ int check_plane8(const adct_plane* p) {
 
 int64_t blocks8(const adct_plane* p) { return (int64_t)(p->height / 8) * (p->width / 8); }
 
+uint32_t grid8(const Args8& a) { return a.spread_rows ? a.spread_rows * kSpread8 : (a.nblk + 255) / 256; }
+
 template <typename S, int OP, bool STORE>
 void launch8(const Args8& a, hipStream_t s) {
-    const dim3 grid(a.spread_rows ? a.spread_rows * kSpread8 : (a.nblk + 255) / 256);
+    const dim3 grid(grid8(a));
     if (a.sse)
         hipLaunchKernelGGL((k_t8<S, OP, STORE, true>), grid, dim3(256), 0, s, a);
     else
@@ -376,9 +401,9 @@ int launch8_typed(int32_t dtype, const Args8& a, hipStream_t s) {
     return launched();
 }
 
-// Shared checks and set-up of the encoders.
-int setup_encoder(const adct_plane* src, void* coef, const adct_plane* dst, int32_t image_height, int64_t* sse,
-                  hipStream_t s, Args8& a) {
+// Shared checks and set-up of the encoders' arguments (no launch).
+int setup_args8(const adct_plane* src, void* coef, const adct_plane* dst, int32_t image_height, int64_t* sse,
+                Args8& a) {
     int rc = check_plane8(src);
     if (rc) return rc;
     if ((rc = check_plane8(dst))) return rc;
@@ -400,14 +425,75 @@ int setup_encoder(const adct_plane* src, void* coef, const adct_plane* dst, int3
         const uint32_t chunks = (a.nblk + 255) / 256;
         const uint32_t image_blocks = (uint32_t)(image_height / 8) * a.bw;
         if (image_blocks / 256 > kSpreadMin8) a.spread_rows = (chunks + kSpread8 - 1) / kSpread8;
-        const uint32_t nimg = (uint32_t)(src->height / image_height);
-        hipLaunchKernelGGL(k_t8_zero, dim3((nimg + 255) / 256), dim3(256), 0, s, a.sse, nimg);
-        return launched();
     }
     return ADCT_OK;
 }
 
+// Checks, argument set-up and the clear of the SSE outputs of one encoder call.
+int setup_encoder(const adct_plane* src, void* coef, const adct_plane* dst, int32_t image_height, int64_t* sse,
+                  hipStream_t s, Args8& a) {
+    const int rc = setup_args8(src, coef, dst, image_height, sse, a);
+    if (rc || !sse) return rc;
+    const uint32_t nimg = (uint32_t)(src->height / image_height);
+    hipLaunchKernelGGL(k_t8_zero, dim3((nimg + 255) / 256), dim3(256), 0, s, a.sse, nimg);
+    return launched();
+}
+
+template <typename S, bool STORE, bool SSE>
+void launch8_planes(const Set8& ps, uint32_t grid, hipStream_t s) {
+    hipLaunchKernelGGL((k_t8_planes<S, kQuant8, STORE, SSE>), dim3(grid), dim3(256), 0, s, ps);
+}
+
+template <typename S>
+void launch8_planes_typed(const Set8& ps, uint32_t grid, bool store, bool sse, hipStream_t s) {
+    if (store) {
+        if (sse) launch8_planes<S, true, true>(ps, grid, s); else launch8_planes<S, true, false>(ps, grid, s);
+    } else {
+        if (sse) launch8_planes<S, false, true>(ps, grid, s); else launch8_planes<S, false, false>(ps, grid, s);
+    }
+}
+
 }  // namespace
+
+int t8_encode_quant_planes(const adct_quant_job* jobs, int32_t njobs, int qp, void* stream) {
+    float qs[5], dqs[5];
+    if (!quant_scales8(qp, qs, dqs)) return ADCT_E_ARG;
+    const bool store = jobs[0].q != nullptr, want_sse = jobs[0].sse != nullptr;
+    const int32_t dt = jobs[0].src.dtype;
+    Set8 ps{};
+    ZeroSet<ADCT_MAX_PLANES> zs{};
+    uint64_t grid = 0;
+    for (int32_t i = 0; i < njobs; ++i) {
+        const adct_quant_job& j = jobs[i];
+        if (j.src.dtype != dt || (j.q != nullptr) != store || (j.sse != nullptr) != want_sse) return ADCT_E_ARG;
+        Args8& a = ps.p[i];
+        const int rc = setup_args8(&j.src, j.q, &j.dst, j.image_height, j.sse, a);
+        if (rc) return rc;
+        for (int c = 0; c < 5; ++c) {
+            a.qs[c] = qs[c];
+            a.dqs[c] = dqs[c];
+        }
+        ps.first[i] = (uint32_t)grid;
+        grid += grid8(a);
+        if (want_sse) {
+            zs.p[i] = a.sse;
+            zs.n[i] = (uint32_t)(j.src.height / j.image_height);
+        }
+    }
+    if (grid > (uint64_t)INT32_MAX) return ADCT_E_TOO_LARGE;
+    ps.n = (uint32_t)njobs;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (want_sse) {
+        zs.count = (uint32_t)njobs;
+        clear_sets(zs, s);
+    }
+    if (dt == ADCT_U8)
+        launch8_planes_typed<uint8_t>(ps, (uint32_t)grid, store, want_sse, s);
+    else
+        launch8_planes_typed<int16_t>(ps, (uint32_t)grid, store, want_sse, s);
+    return launched();
+}
+
 }  // namespace adct
 
 using namespace adct;

@@ -1,11 +1,15 @@
 """GPU parity of adct_encode_quant_planes: several planes coded in one launch
-must give exactly what adct_encode_quant gives on each plane alone (levels,
-reconstruction, per-image SSE), and a sample the oracle's values; each job
-writes only its own outputs; bad job sets are refused before any launch."""
+must give exactly what the per-plane encoder of the same block size
+(adct_encode_quant, adct_t8_encode_quant, adct_t32_encode_quant) gives on
+each plane alone (levels, reconstruction, per-image SSE), and a sample the
+oracle's values; each job writes only its own outputs; bad job sets are
+refused before any launch."""
 import numpy as np
 import pytest
 
 from oracle import adct_oracle as O
+from oracle import t8 as T8
+from oracle import t32 as T32
 import synth
 
 torch = pytest.importorskip("torch")
@@ -18,26 +22,36 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-def _alone(x, qp, ih, store, want_sse):
+ALONE = {16: adct.encode_quant, 8: adct.t8_encode_quant, 32: adct.t32_encode_quant}
+
+
+def _levels(x, block, fill=None):
+    shape = (x.numel() // (block * block), block, block)
+    if fill is None:
+        return torch.empty(shape, dtype=torch.int16, device="cuda")
+    return torch.full(shape, fill, dtype=torch.int16, device="cuda")
+
+
+def _alone(x, qp, ih, store, want_sse, block):
     out = torch.empty_like(x)
-    q = torch.empty((x.numel() // 256, 16, 16), dtype=torch.int16, device="cuda") if store else None
-    s = adct.encode_quant(x, qp, out, q=q, image_height=ih, want_sse=want_sse)
+    q = _levels(x, block) if store else None
+    s = ALONE[block](x, qp, out, q=q, image_height=ih, want_sse=want_sse)
     torch.cuda.synchronize()
     return out, q, s
 
 
-def _run_and_compare(xs, ihs, qp, store=True, want_sse=True):
+def _run_and_compare(xs, ihs, qp, store=True, want_sse=True, block=16):
     jobs, outs, qs = [], [], []
     for x, ih in zip(xs, ihs):
         o = torch.full_like(x, 77)
-        q = torch.full((x.numel() // 256, 16, 16), -5, dtype=torch.int16, device="cuda") if store else None
+        q = _levels(x, block, -5) if store else None
         jobs.append((x, o, q, ih))
         outs.append(o)
         qs.append(q)
-    sses = adct.encode_quant_planes(jobs, qp, want_sse=want_sse)
+    sses = adct.encode_quant_planes(jobs, qp, block=block, want_sse=want_sse)
     torch.cuda.synchronize()
     for k, (x, ih) in enumerate(zip(xs, ihs)):
-        o1, q1, s1 = _alone(x, qp, ih, store, want_sse)
+        o1, q1, s1 = _alone(x, qp, ih, store, want_sse, block)
         assert torch.equal(outs[k], o1), k
         if store:
             assert torch.equal(qs[k], q1), k
@@ -71,6 +85,44 @@ def test_video_frame_planes_match_single_calls(qp):
     assert np.array_equal(outs[2][544:1088].cpu().numpy(), want)
     assert np.array_equal(qs[2][2040:4080].cpu().numpy(), wq)
     assert int(sses[2][1].item()) == O.sse(want, v)
+
+
+@pytest.mark.parametrize("qp", [0, 27, 51])
+@pytest.mark.parametrize("block", [8, 32])
+def test_video_frame_planes_other_blocks(block, qp):
+    # the same frame stacks with T8 on 8x8 and T32 on 32x32 blocks (every
+    # plane side is a multiple of 32); the oracle on the first frame's U plane
+    print(f"[planes] video block={block} qp={qp}", flush=True)
+    ys = _frames(3)
+    xs = [dev(p) for p in ys]
+    outs, qs, sses = _run_and_compare(xs, [1088, 544, 544], qp, block=block)
+    u = ys[1][:544]
+    if block == 8:
+        wq, want = T8.quant_reconstruct8(u, qp, lo=-255, hi=255)
+    else:
+        wq, _, want = T32.quant_reconstruct_32(u, qp, lo=-255, hi=255)
+    nb = u.size // (block * block)
+    assert np.array_equal(outs[1][:544].cpu().numpy(), want)
+    assert np.array_equal(qs[1][:nb].cpu().numpy(), wq)
+    assert int(sses[1][0].item()) == O.sse(want, u)
+
+
+@pytest.mark.parametrize("block", [8, 32])
+@pytest.mark.parametrize("kind", ["u8", "i16"])
+def test_mixed_plane_sizes_other_blocks(kind, block):
+    # 8 planes of block-multiple sides: ragged workgroups, one block, images
+    # straddling workgroups, interleaved and plain SSE orders side by side
+    b = block
+    shapes = [((3 * b, 5 * b), 3 * b), ((b, b), b), ((6 * b, 10 * b), 2 * b), ((1024, 1024), 512), ((4 * b, 3 * b), b),
+              ((2048, 2048), 2048), ((17 * b, 4 * b), 17 * b), ((32 * b, 9 * b), 8 * b)]
+    xs = []
+    for k, ((h, w), ih) in enumerate(shapes):
+        if kind == "u8":
+            xs.append(dev(synth.ar1_batch(h // ih, ih, w, seed_base=32_000 + 10 * k)))
+        else:
+            xs.append(dev(synth.laplacian_residual(32_000 + k, h, w)))
+    _run_and_compare(xs, [ih for _, ih in shapes], 22, True, True, block)
+    _run_and_compare(xs, [ih for _, ih in shapes], 37, False, False, block)
 
 
 @pytest.mark.parametrize("store,want_sse", [(True, True), (True, False), (False, True), (False, False)])
@@ -126,3 +178,16 @@ def test_bad_job_sets():
     with pytest.raises(adct.AdctError) as e:
         adct.encode_quant_planes([(a, torch.empty_like(a))], 64)
     assert e.value.code == adct.E_ARG
+    with pytest.raises(adct.AdctError) as e:
+        adct.encode_quant_planes([(a, torch.empty_like(a))], 27, block=4)
+    assert e.value.code == adct.E_ARG
+    # a 32-point job whose sides are not multiples of 32, an 8-point job
+    # whose image height is not a multiple of 8
+    c = torch.zeros((48, 64), dtype=torch.uint8, device="cuda")
+    with pytest.raises(adct.AdctError) as e:
+        adct.encode_quant_planes([(c, torch.empty_like(c))], 27, block=32)
+    assert e.value.code == adct.E_SHAPE
+    with pytest.raises(adct.AdctError) as e:
+        adct.encode_quant_planes([(c, torch.empty_like(c), None, 12, torch.empty(4, dtype=torch.int64, device="cuda"))],
+                                 27, block=8)
+    assert e.value.code == adct.E_SHAPE
