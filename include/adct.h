@@ -392,6 +392,53 @@ int adct_t32_encode_zonal(const adct_plane* src, int r, int32_t* coef, const adc
 int adct_t32_encode_quant(const adct_plane* src, int qp, int16_t* q, const adct_plane* dst,
                           int32_t image_height, int64_t* sse, void* stream);
 
+/* ---- the 64-point extension on 64x64 blocks ------------------------- */
+/* The same construction one level further: T64 = P64 diag(T32, T32) B64,
+ * B64 folding a row into the sums x_j + x_{63-j} and differences
+ * x_j - x_{63-j}, T32 transforming each half and P64 interleaving them
+ * (coefficient 2k from the sums, 2k + 1 from the differences): 304
+ * additions, entries in {0, +1, -1}, and T64 T64^T = diag(2 d32[u / 2]),
+ * entries 16, 32 or 64.  The 64x64 codec mirrors the 32x32 one with zonal
+ * weights W64 = 4096 / (d_u d_v), quantiser tables qs = fp32(s_u s_v /
+ * Delta), dqs = fp32(4096 Delta s_u s_v), levels rounded half away from
+ * zero and saturated to int16, reconstruction clamp(floor((R + 2048) /
+ * 4096)).  Planes: sides multiples of 64 (else ADCT_E_SHAPE), sample (0,0)
+ * and the pitch 16-byte aligned (else ADCT_E_ALIGN), int16 samples within
+ * [-2047, 2047]; coefficient arrays are block-major [nblk64][64][64], block
+ * k = by * (width/64) + bx, element u*64 + v, 16-byte aligned; image_height
+ * a multiple of 64. */
+
+/* Host copies of T64 (row-major), the diagonal of S64 and W64. */
+int adct_t64_constants(int32_t* T4096, double* s64, int32_t* W4096);
+
+/* Host copies of the 64x64 quantisation tables for `qp` in [0, 63]. */
+int adct_t64_quant_tables(int qp, float* qs4096, float* dqs4096);
+
+/* The kernels' 64-point butterflies run on the host with every addition
+ * and subtraction counted (which = 0: T64, 1: T64^T); 64 values in and out. */
+int adct_t64_host_butterfly_count(int32_t which, const int32_t* in64, int32_t* out64, int64_t* additions);
+
+/* Y = T64 A T64^T for every 64x64 block A of src (U8 or I16); coef: device
+ * int32 [nblk64][64][64]. */
+int adct_t64_fwd2d(const adct_plane* src, int32_t* coef, void* stream);
+
+/* T64^T Y T64 for every block (block-major int32 in and out; exact while
+ * every partial sum stays within int32, which holds for |Y| < 2^18). */
+int adct_t64_inv2d(const int32_t* coef, int64_t nblk, int32_t* out, void* stream);
+
+/* Single-pass 64x64 encoder with reconstruction, zonal form: Y stored to
+ * coef unless NULL, the top-left r x r coefficients kept with S64 folded in
+ * (r in [0, 64]), inverse, rounding and clamping into dst ([0, 255] for U8,
+ * [-255, 255] for I16), and the exact per-image SSE when sse is non-NULL. */
+int adct_t64_encode_zonal(const adct_plane* src, int r, int32_t* coef, const adct_plane* dst,
+                          int32_t image_height, int64_t* sse, void* stream);
+
+/* Single-pass 64x64 encoder, quantised form: levels stored unless NULL,
+ * dequantisation to 12 fractional bits, inverse, rounding, clamping and the
+ * optional SSE. */
+int adct_t64_encode_quant(const adct_plane* src, int qp, int16_t* q, const adct_plane* dst,
+                          int32_t image_height, int64_t* sse, void* stream);
+
 /* ---- mixed 8/16-point coding ------------------------------------------ */
 /* The codec of the second video scenario of Section 3.2, in which both the
  * 8-point (T8) and the 16-point (T) transforms are the approximations.  The

@@ -123,6 +123,13 @@ _SIGNATURES = {
     "adct_t32_fwd2d": (ctypes.c_int, [_PP, _P, _P]),
     "adct_t32_inv2d": (ctypes.c_int, [_P, _I64, _P, _P]),
     "adct_t32_encode_zonal": (ctypes.c_int, [_PP, ctypes.c_int, _P, _PP, _I32, _P, _P]),
+    "adct_t64_constants": (ctypes.c_int, [_P, _P, _P]),
+    "adct_t64_quant_tables": (ctypes.c_int, [ctypes.c_int, _P, _P]),
+    "adct_t64_host_butterfly_count": (ctypes.c_int, [_I32, _P, _P, ctypes.POINTER(_I64)]),
+    "adct_t64_fwd2d": (ctypes.c_int, [_PP, _P, _P]),
+    "adct_t64_inv2d": (ctypes.c_int, [_P, _I64, _P, _P]),
+    "adct_t64_encode_zonal": (ctypes.c_int, [_PP, ctypes.c_int, _P, _PP, _I32, _P, _P]),
+    "adct_t64_encode_quant": (ctypes.c_int, [_PP, ctypes.c_int, _P, _PP, _I32, _P, _P]),
     "adct_t32_encode_quant": (ctypes.c_int, [_PP, ctypes.c_int, _P, _PP, _I32, _P, _P]),
     "adct_check": (ctypes.c_int, [_P]),
     "adct_recon": (ctypes.c_int, [_P, _PP, _P]),
@@ -579,6 +586,70 @@ def t32_encode_quant(src, qp: int, dst, q=None, image_height=None, sse=None, wan
     ih, sse, sp = _sse_out(src, image_height, sse, want_sse)
     _check(_lib().adct_t32_encode_quant(ctypes.byref(ps), qp, q.data_ptr() if q is not None else None,
                                         ctypes.byref(pd), ih, sp, _stream(stream)), "t32_encode_quant")
+    return sse
+
+
+def t64_constants():
+    """(T64 int32 64x64, s64 float64 [64], W64 int32 64x64)."""
+    T = np.empty(4096, np.int32)
+    s = np.empty(64, np.float64)
+    W = np.empty(4096, np.int32)
+    _check(_lib().adct_t64_constants(T.ctypes.data, s.ctypes.data, W.ctypes.data), "t64_constants")
+    return T.reshape(64, 64), s, W.reshape(64, 64)
+
+
+def t64_quant_tables(qp: int):
+    qs = np.empty(4096, np.float32)
+    dqs = np.empty(4096, np.float32)
+    _check(_lib().adct_t64_quant_tables(qp, qs.ctypes.data, dqs.ctypes.data), "t64_quant_tables")
+    return qs.reshape(64, 64), dqs.reshape(64, 64)
+
+
+def t64_host_butterfly_count(x, inverse: bool = False):
+    """(output, additions) of the kernels' 64-point butterfly run on the host."""
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.int32).reshape(64))
+    y = np.empty(64, np.int32)
+    n = _I64(0)
+    _check(_lib().adct_t64_host_butterfly_count(1 if inverse else 0, x.ctypes.data, y.ctypes.data, ctypes.byref(n)),
+           "t64_host_butterfly_count")
+    return y, n.value
+
+
+def _nblk64(src):
+    return (src.shape[0] // 64) * (src.shape[1] // 64)
+
+
+def t64_fwd2d(src, coef=None, stream=None):
+    torch = _torch()
+    if coef is None:
+        coef = torch.empty((_nblk64(src), 64, 64), dtype=torch.int32, device=src.device)
+    p = plane(src)
+    _check(_lib().adct_t64_fwd2d(ctypes.byref(p), coef.data_ptr(), _stream(stream)), "t64_fwd2d")
+    return coef
+
+
+def t64_inv2d(coef, out=None, stream=None):
+    torch = _torch()
+    n = coef.numel() // 4096
+    if out is None:
+        out = torch.empty_like(coef)
+    _check(_lib().adct_t64_inv2d(coef.data_ptr(), n, out.data_ptr(), _stream(stream)), "t64_inv2d")
+    return out
+
+
+def t64_encode_zonal(src, r: int, dst, coef=None, image_height=None, sse=None, want_sse=True, stream=None):
+    ps, pd = plane(src), plane(dst)
+    ih, sse, sp = _sse_out(src, image_height, sse, want_sse)
+    _check(_lib().adct_t64_encode_zonal(ctypes.byref(ps), r, coef.data_ptr() if coef is not None else None,
+                                        ctypes.byref(pd), ih, sp, _stream(stream)), "t64_encode_zonal")
+    return sse
+
+
+def t64_encode_quant(src, qp: int, dst, q=None, image_height=None, sse=None, want_sse=True, stream=None):
+    ps, pd = plane(src), plane(dst)
+    ih, sse, sp = _sse_out(src, image_height, sse, want_sse)
+    _check(_lib().adct_t64_encode_quant(ctypes.byref(ps), qp, q.data_ptr() if q is not None else None,
+                                        ctypes.byref(pd), ih, sp, _stream(stream)), "t64_encode_quant")
     return sse
 
 

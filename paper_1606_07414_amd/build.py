@@ -11,7 +11,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libadct.so")
 
 SOURCES = ["adct_host.cpp", "adct_policy.cpp", "adct_plain.hip", "adct_batch.hip", "adct_server.hip", "adct_metrics.hip",
-           "adct_t8.hip", "adct_t32.hip", "adct_compare.hip", "adct_mixed.hip", "adct_sync.hip"]
+           "adct_t8.hip", "adct_t32.hip", "adct_t64.hip", "adct_compare.hip", "adct_mixed.hip", "adct_sync.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",

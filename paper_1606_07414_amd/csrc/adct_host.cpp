@@ -9,6 +9,7 @@
 #include "adct_internal.hpp"
 #include "adct_t8_common.hpp"
 #include "adct_t32_common.hpp"
+#include "adct_t64_common.hpp"
 #include "adct_round.hpp"
 
 namespace adct {
@@ -238,6 +239,59 @@ int adct_t32_host_butterfly_count(int32_t which, const int32_t* in32, int32_t* o
     for (int i = 0; i < 32; ++i) {
         if (y[i].v < INT32_MIN || y[i].v > INT32_MAX) return ADCT_E_ARG;
         out32[i] = (int32_t)y[i].v;
+    }
+    *additions = CountedInt::ops;
+    return ADCT_OK;
+}
+
+// Entry (u, j) of T32 = P32 diag(T, T) B32.
+static int t32_entry(int u, int j) {
+    const int k = u >> 1, sgn = (u & 1) ? -1 : 1;
+    return j < 16 ? kT[k][j] : sgn * kT[k][31 - j];
+}
+
+int adct_t64_constants(int32_t* T4096, double* s64, int32_t* W4096) {
+    // T64 = P64 diag(T32, T32) B64: row 2k is row k of T32 on the folded sums
+    // (T64[2k][j] = T64[2k][63-j] = T32[k][j]), row 2k+1 row k of T32 on the
+    // folded differences (T64[2k+1][j] = -T64[2k+1][63-j] = T32[k][j])
+    for (int u = 0; u < 64; ++u) {
+        const int k = u >> 1, odd = u & 1;
+        if (T4096)
+            for (int j = 0; j < 32; ++j) {
+                T4096[u * 64 + j] = t32_entry(k, j);
+                T4096[u * 64 + 63 - j] = odd ? -t32_entry(k, j) : t32_entry(k, j);
+            }
+        if (s64) s64[u] = 1.0 / sqrt((double)(1 << l64(u)));
+        if (W4096)
+            for (int v = 0; v < 64; ++v) W4096[u * 64 + v] = 4096 >> (l64(u) + l64(v));
+    }
+    return ADCT_OK;
+}
+
+int adct_t64_quant_tables(int qp, float* qs4096, float* dqs4096) {
+    float qs[5], dqs[5];
+    if (!quant_scales64(qp, qs, dqs)) return ADCT_E_ARG;
+    for (int u = 0; u < 64; ++u)
+        for (int v = 0; v < 64; ++v) {
+            const int c = l64(u) + l64(v) - 8;
+            if (qs4096) qs4096[u * 64 + v] = qs[c];
+            if (dqs4096) dqs4096[u * 64 + v] = dqs[c];
+        }
+    return ADCT_OK;
+}
+
+int adct_t64_host_butterfly_count(int32_t which, const int32_t* in64, int32_t* out64, int64_t* additions) {
+    if (!in64 || !out64 || !additions || which < 0 || which > 1) return ADCT_E_ARG;
+    CountedInt x[64], y[64];
+    CountedInt::ops = 0;
+    for (int i = 0; i < 64; ++i) x[i].v = in64[i];
+    if (which == 0)
+        fwd64(x, y);
+    else
+        inv64(x, y);
+    for (int i = 0; i < 64; ++i) {
+        if (y[i].v < INT32_MIN || y[i].v > INT32_MAX) return ADCT_E_ARG;
+        out64[i] = (int32_t)y[i].v;
     }
     *additions = CountedInt::ops;
     return ADCT_OK;

@@ -452,6 +452,31 @@ def test_t32_kernel_butterflies_count_120_and_match_oracle():
         assert n == 120 and np.array_equal(x, A.T @ v)
 
 
+def test_t64_constants_and_tables_match_oracle():
+    from oracle import t64 as T64
+    T, s, W = adct.t64_constants()
+    assert np.array_equal(T, T64.transform_matrix_64())
+    assert np.array_equal(s, T64.scaling_vector_64())
+    assert np.array_equal(W, T64.zonal_weights_64())
+    for qp in (0, 4, 15, 16, 22, 27, 37, 51, 63):
+        qs, dqs = adct.t64_quant_tables(qp)
+        oqs, odqs = T64.quant_tables_64(qp)
+        assert np.array_equal(qs.view(np.uint32), oqs.view(np.uint32)), qp
+        assert np.array_equal(dqs.view(np.uint32), odqs.view(np.uint32)), qp
+
+
+def test_t64_kernel_butterflies_count_304_and_match_oracle():
+    from oracle import t64 as T64
+    A = T64.transform_matrix_64()
+    rng = np.random.default_rng(64)
+    vecs = list(np.eye(64, dtype=np.int64)) + [rng.integers(-131008, 131009, 64) for _ in range(100)]
+    for v in vecs:
+        y, n = adct.t64_host_butterfly_count(v)
+        assert n == 304 and np.array_equal(y, A @ v)
+        x, n = adct.t64_host_butterfly_count(v, inverse=True)
+        assert n == 304 and np.array_equal(x, A.T @ v)
+
+
 def test_serving_constants_match_header():
     import re
     with open(os.path.join(ROOT, "include", "adct.h")) as f:
