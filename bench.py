@@ -61,7 +61,8 @@ CAPACITY_RATES = (5000, 7500, 10000, 15000, 20000)   # req/s, for the capacity s
 CAPACITY_P99_MS = 1.0
 
 
-LEGS = ("zigzag", "t32", "single", "video", "batch", "serving")
+LEGS = ("zigzag", "t32", "t64", "single", "video", "batch", "serving")
+IMAGE_LEGS = ("zigzag", "t32", "t64")  # legs on the batched images (their buffers are freed after them)
 
 
 def recon_bytes_per_tile(r: int) -> int:
@@ -332,6 +333,28 @@ def t32_images(torch, adct, stream, x, n_img):
     return res
 
 
+T64_RS = (8, 16, 32, 48, 64)
+
+
+def t64_images(torch, adct, stream, x, n_img):
+    """The 64-point extension on the batched images (64x64 blocks, 65536 of
+    them): per r the single-pass encoder keeping the top-left r x r
+    coefficients (int32 coefficients, reconstruction, per-image SSE), its
+    time and mean PSNR.  4096 + 16384 + 4096 bytes per 64x64 block."""
+    nblk = x.numel() // 4096
+    coef = torch.empty((nblk, 64, 64), dtype=torch.int32, device="cuda")
+    out = torch.empty_like(x)
+    sse = torch.empty(n_img, dtype=torch.int64, device="cuda")
+    res = {"blocks64": nblk, "bytes_per_block64": 24576, "additions_per_64_point_transform": 304, "r": {}}
+    for r in T64_RS:
+        ms = timed(torch, lambda: adct.t64_encode_zonal(x, r, out, coef=coef, image_height=SIDE, sse=sse,
+                                                        stream=stream), 10, stream)
+        gbs = 24576 * nblk / (ms * 1e-3) / 1e9
+        res["r"][r] = {"ms": ms, "blocks64_per_s": nblk / (ms * 1e-3), "gbs": gbs, "frac_of_8tbs": gbs / HBM_PEAK_GBS,
+                       "psnr_db": float(np.mean(adct.psnr(sse.cpu().numpy(), SIDE * SIDE)))}
+    return res
+
+
 def uneven_batch(torch, adct, stream, n=4096):
     """4096 uint8 images with sides uniform over the multiples of 16 in
     [64, 2048], coded by one persistent, graph-captured launch (autotuned):
@@ -574,6 +597,9 @@ def summary_line(full: dict) -> dict:
         t = other.get("t32_images_1024x512x512")
         if t:
             summ["t32_zonal_frac"] = {str(r): round(v["frac_of_8tbs"], 3) for r, v in t["r"].items()}
+        t = other.get("t64_images_1024x512x512")
+        if t:
+            summ["t64_zonal_frac"] = {str(r): round(v["frac_of_8tbs"], 3) for r, v in t["r"].items()}
         zz = other.get("image_experiment_zigzag_1024x512x512")
         if zz:
             summ["zigzag_psnr_db"] = {str(r): round(v["psnr_db"], 2) for r, v in zz["r"].items() if r in (10, 45, 150)}
@@ -730,6 +756,7 @@ def main():
                 ("zigzag", "image_experiment_zigzag_1024x512x512",
                  lambda: image_experiment(torch, adct, stream, x, coef, out, n_img)),
                 ("t32", "t32_images_1024x512x512", lambda: t32_images(torch, adct, stream, x, n_img)),
+                ("t64", "t64_images_1024x512x512", lambda: t64_images(torch, adct, stream, x, n_img)),
                 ("single", "single_image_256x256", lambda: single_image(torch, adct, stream)),
                 ("video", "video_residuals_64x1920x1088", lambda: video(torch, adct, stream)),
                 ("batch", "uneven_batch_4096", lambda: uneven_batch(torch, adct, stream)),
@@ -739,8 +766,8 @@ def main():
             t0 = time.perf_counter()
             other[name] = fn()
             other[name]["wall_s"] = time.perf_counter() - t0
-            if leg == "t32":  # the last leg on the batched images
-                del coef, out, sse
+            if leg in IMAGE_LEGS and not any(g in IMAGE_LEGS[IMAGE_LEGS.index(leg) + 1:] for g in legs):
+                del coef, out, sse  # the last leg on the batched images
             torch.cuda.empty_cache()
             print(f"[bench] {name} done in {other[name]['wall_s']:.1f} s", file=sys.stderr, flush=True)
         full["other_workloads"] = other

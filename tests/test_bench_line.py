@@ -41,6 +41,8 @@ def _full_result():
                                                            "dma_copies": 400} for pol in ("adaptive", "by_size")}
                                                for lam in bench.SERVE_POLICY_RATES}},
             "image_experiment_zigzag_1024x512x512": {"r": {r: {"psnr_db": 30.0} for r in bench.ZIGZAG_R}},
+            "t32_images_1024x512x512": {"r": {r: {"frac_of_8tbs": 0.7} for r in bench.T32_RS}},
+            "t64_images_1024x512x512": {"r": {r: {"frac_of_8tbs": 0.5} for r in bench.T64_RS}},
         },
         "detail_file": "gpurun_out/bench_detail.json",
     }
@@ -58,6 +60,7 @@ def test_summary_line_is_compact_and_complete():
         assert k in line["roofline"], k
     assert set(line["cpu_baseline"]) == {"value", "unit", "cores", "kind", "sample"}
     assert "\n" not in text
+    assert set(line["other_workloads"]["t64_zonal_frac"]) == {str(r) for r in bench.T64_RS}
     assert set(line["other_workloads"]["serving_p99_ms_dma_adaptive_vs_by_size"]) == \
         {str(lam) for lam in bench.SERVE_POLICY_RATES}
 

@@ -161,6 +161,13 @@ def test_t64_full_size_sampled():
     s = host(adct.t64_encode_zonal(x, 64, out, coef=coef, image_height=512))
     assert torch.equal(out, x) and not s.any()  # r = 64 keeps everything: lossless
     s = host(adct.t64_encode_zonal(x, 16, out, coef=coef, image_height=512))
+    # on every image: keeping 16 x 16 of each 64x64 block is the same
+    # projection as keeping 8 x 8 of each 32x32 block (the construction's
+    # rows pair up into the 32-point rows on each half), bit for bit
+    out32 = torch.empty_like(x)
+    s32 = host(adct.t32_encode_zonal(x, 8, out32, image_height=512))
+    assert torch.equal(out, out32) and np.array_equal(s, s32)
+    del out32
     for k in (0, 511, 1023):
         sub = img[512 * k:512 * (k + 1)]
         want = T64.zonal_reconstruct_64(sub, 16)

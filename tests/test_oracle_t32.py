@@ -111,6 +111,20 @@ def test_weighted_round_trip_is_1024x_and_tile_mean():
     assert np.array_equal(T32.zonal_reconstruct_32(res, 32, -255, 255), res)
 
 
+def test_zonal_with_even_r_equals_16_point_with_half_r():
+    # T's rows are symmetric or antisymmetric (Section 2.1 builds them from
+    # folded sums and differences), so rows 2k and 2k + 1 of T32 (k < m) span
+    # row k of T on each 16-sample half: keeping 2m x 2m coefficients of a
+    # 32x32 block projects onto the same subspace as keeping m x m of each of
+    # its four 16x16 blocks.  Both zonal codecs are that exact projection,
+    # rounded half up, so they agree sample for sample.
+    img = np.random.default_rng(12).integers(0, 256, (64, 96)).astype(np.uint8)
+    for m in (0, 1, 2, 3, 4, 8, 13, 16):
+        assert np.array_equal(T32.zonal_reconstruct_32(img, 2 * m), O.zonal_reconstruct(img, m)), m
+    # an odd r keeps an even row without its odd partner: no such identity
+    assert not np.array_equal(T32.zonal_reconstruct_32(img, 3), O.zonal_reconstruct(img, 1))
+
+
 def test_zonal_weights_are_shifts():
     W = T32.zonal_weights_32()
     assert set(np.unique(W)) == {1, 2, 4, 8, 16}

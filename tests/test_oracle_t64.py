@@ -116,6 +116,23 @@ def test_weighted_round_trip_is_4096x_and_tile_mean():
     assert np.array_equal(T64.zonal_reconstruct_64(res, 64, -255, 255), res)
 
 
+def test_zonal_with_even_r_equals_32_point_with_half_r():
+    # T32's rows are symmetric (even k) or antisymmetric (odd k), so rows 2k
+    # and 2k + 1 of T64 (k < m) span row k of T32 on each 32-sample half:
+    # keeping 2m x 2m coefficients of a 64x64 block projects onto the same
+    # subspace as keeping m x m of each of its four 32x32 blocks.  Both zonal
+    # codecs are that exact projection, rounded half up, so they agree sample
+    # for sample, on samples and on residuals.
+    rng = np.random.default_rng(22)
+    img = rng.integers(0, 256, (128, 192)).astype(np.uint8)
+    res = rng.integers(-255, 256, (64, 128)).astype(np.int16)
+    for m in (0, 1, 2, 5, 8, 16, 27, 32):
+        assert np.array_equal(T64.zonal_reconstruct_64(img, 2 * m), T32.zonal_reconstruct_32(img, m)), m
+        assert np.array_equal(T64.zonal_reconstruct_64(res, 2 * m, -255, 255),
+                              T32.zonal_reconstruct_32(res, m, -255, 255)), m
+    assert not np.array_equal(T64.zonal_reconstruct_64(img, 5), T32.zonal_reconstruct_32(img, 2))
+
+
 def test_zonal_weights_are_shifts():
     W = T64.zonal_weights_64()
     assert set(np.unique(W)) == {1, 2, 4, 8, 16}
