@@ -22,6 +22,14 @@ def test_captured_encoders_replay_like_eager():
     q = torch.empty((x.numel() // 256, 16, 16), dtype=torch.int16, device="cuda")
     s_z, s_q, s_g = (torch.empty(4, dtype=torch.int64, device="cuda") for _ in range(3))
     ss = torch.empty(4, dtype=torch.float64, device="cuda")
+    # several planes in one launch (one clear of both SSE arrays), and the
+    # 32x32 and 64x64 codecs, on planes whose sides are multiples of 64
+    y = torch.from_numpy(synth.ar1_batch(2, 128, 192, seed_base=4010)).cuda()
+    u = torch.from_numpy(synth.ar1_batch(2, 64, 128, seed_base=4020)).cuda()
+    out_y, out_u, out_32, out_64 = (torch.empty_like(t) for t in (y, u, y, y))
+    q_y = torch.empty((y.numel() // 256, 16, 16), dtype=torch.int16, device="cuda")
+    q_u = torch.empty((u.numel() // 256, 16, 16), dtype=torch.int16, device="cuda")
+    s_y, s_u, s_32, s_64 = (torch.empty(2, dtype=torch.int64, device="cuda") for _ in range(4))
     side = torch.cuda.Stream()
 
     def work(stream):
@@ -29,11 +37,15 @@ def test_captured_encoders_replay_like_eager():
         adct.encode_quant(x, 27, out_q, q=q, image_height=128, sse=s_q, stream=stream)
         adct.encode_zigzag(x, 45, out_g, image_height=128, sse=s_g, stream=stream)
         adct.ssim(x, out_g, image_height=128, out=ss, stream=stream)
+        adct.encode_quant_planes([(y, out_y, q_y, 128, s_y), (u, out_u, q_u, 64, s_u)], 32, stream=stream)
+        adct.t32_encode_quant(y, 22, out_32, image_height=128, sse=s_32, stream=stream)
+        adct.t64_encode_zonal(y, 12, out_64, image_height=128, sse=s_64, stream=stream)
 
     # eager reference
     work(torch.cuda.current_stream())
     torch.cuda.synchronize()
-    want = [t.clone() for t in (out_z, out_q, out_g, coef, q, s_z, s_q, s_g, ss)]
+    extra = (out_y, out_u, q_y, q_u, s_y, s_u, out_32, s_32, out_64, s_64)
+    want = [t.clone() for t in (out_z, out_q, out_g, coef, q, s_z, s_q, s_g) + extra + (ss,)]
     assert np.array_equal(want[0].cpu().numpy(), O.zonal_reconstruct(img, 8))
     assert np.array_equal(want[2].cpu().numpy(), E.zigzag_reconstruct(img, 45))
 
@@ -44,12 +56,12 @@ def test_captured_encoders_replay_like_eager():
             work(side)
     torch.cuda.synchronize()
     for rep in range(4):
-        for t in (out_z, out_q, out_g, coef, q, s_z, s_q, s_g, ss):  # eager work between replays
+        for t in (out_z, out_q, out_g, coef, q, s_z, s_q, s_g, ss) + extra:  # eager work between replays
             t.fill_(rep + 1)
         torch.cuda.synchronize()
         g.replay()
         torch.cuda.synchronize()
-        got = (out_z, out_q, out_g, coef, q, s_z, s_q, s_g)
+        got = (out_z, out_q, out_g, coef, q, s_z, s_q, s_g) + extra
         for k, (a, b) in enumerate(zip(got, want)):
             assert torch.equal(a, b), (rep, k)
         # SSIM sums in an order that is not fixed: equal to rounding
