@@ -140,8 +140,12 @@ __device__ __forceinline__ void column_factors32(const Scale5& t, int v, float (
     for (int l = 3; l <= 5; ++l) out[l - 3] = pick5(t, l + lv - 6);
 }
 
-// Workgroup b of a launch over the plane of `a` (256 threads).
-template <typename S, int OP, bool STORE, bool SSE>
+// Workgroup b of a launch over the plane of `a` (256 threads).  RB bounds
+// the zonal size at compile time (r <= RB): the coefficients with u or v >=
+// RB are then known zeros, and the inverse passes, unrolled, drop every
+// addition of such a zero (a zonal launch takes the least of 8, 16 and 32
+// that holds r).
+template <typename S, int OP, bool STORE, bool SSE, int RB = 32>
 __device__ __forceinline__ void t32_group(const Args32& a, uint32_t b) {
     __shared__ __align__(16) int32_t lds[kTiles32 * kTile32];
     __shared__ long long red[4];
@@ -194,7 +198,8 @@ __device__ __forceinline__ void t32_group(const Args32& a, uint32_t b) {
         const bool kv = cv < a.r;
         const int lv = l32(cv);
 #pragma unroll
-        for (int u = 0; u < 32; ++u) Y[u] = (kv && u < a.r) ? (int32_t)((uint32_t)Y[u] << (10 - l32(u) - lv)) : 0;
+        for (int u = 0; u < 32; ++u)
+            Y[u] = (u < RB && kv && u < a.r) ? (int32_t)((uint32_t)Y[u] << (10 - l32(u) - lv)) : 0;
     } else {
         float fq[3], fd[3];
         column_factors32(a.qs, cv, fq);
@@ -226,7 +231,7 @@ __device__ __forceinline__ void t32_group(const Args32& a, uint32_t b) {
         int32_t c[32];
         const int32_t* l = lds + rt * kTile32 + rr * kRow32;
 #pragma unroll
-        for (int j = 0; j < 32; ++j) c[j] = l[j];
+        for (int j = 0; j < 32; ++j) c[j] = j < RB ? l[j] : 0;  // columns v >= RB are zero
         inv32(c, R);
     }
     constexpr int32_t lo = sizeof(S) == 1 ? 0 : -255, hi = 255;
@@ -270,9 +275,9 @@ __device__ __forceinline__ void t32_group(const Args32& a, uint32_t b) {
 constexpr int kInvRow = 36;                     // output staging: words per row
 constexpr int kInvTile = 32 * kInvRow + 4;      // and per tile
 
-template <typename S, int OP, bool STORE, bool SSE>
+template <typename S, int OP, bool STORE, bool SSE, int RB>
 __global__ __launch_bounds__(256) void k_t32(Args32 a) {
-    t32_group<S, OP, STORE, SSE>(a, blockIdx.x);
+    t32_group<S, OP, STORE, SSE, RB>(a, blockIdx.x);
 }
 
 // Several planes in one launch: plane i takes the workgroups from first[i]
@@ -359,13 +364,22 @@ uint32_t grid32(const Args32& a) {
     return a.spread_rows ? a.spread_rows * kSpread32 : (a.nblk + kTiles32 - 1) / kTiles32;
 }
 
-template <typename S, int OP, bool STORE>
-void launch32(const Args32& a, hipStream_t s) {
+template <typename S, int OP, bool STORE, int RB>
+void launch32_rb(const Args32& a, hipStream_t s) {
     const dim3 grid(grid32(a));
     if (a.sse)
-        hipLaunchKernelGGL((k_t32<S, OP, STORE, true>), grid, dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_t32<S, OP, STORE, true, RB>), grid, dim3(256), 0, s, a);
     else
-        hipLaunchKernelGGL((k_t32<S, OP, STORE, false>), grid, dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_t32<S, OP, STORE, false, RB>), grid, dim3(256), 0, s, a);
+}
+
+template <typename S, int OP, bool STORE>
+void launch32(const Args32& a, hipStream_t s) {
+    if constexpr (OP == kZonal32) {
+        if (a.r <= 8) return launch32_rb<S, OP, STORE, 8>(a, s);
+        if (a.r <= 16) return launch32_rb<S, OP, STORE, 16>(a, s);
+    }
+    launch32_rb<S, OP, STORE, 32>(a, s);
 }
 
 template <int OP>

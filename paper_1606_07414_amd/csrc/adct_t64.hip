@@ -140,8 +140,12 @@ __device__ __forceinline__ void column_factors64(const Scale5& t, int v, float (
     for (int l = 4; l <= 6; ++l) out[l - 4] = pick5(t, l + lv - 8);
 }
 
-// Workgroup b of a launch over the plane of `a` (128 threads).
-template <typename S, int OP, bool STORE, bool SSE>
+// Workgroup b of a launch over the plane of `a` (128 threads).  RB bounds
+// the zonal size at compile time (r <= RB): the coefficients with u or v >=
+// RB are then known zeros, and the inverse passes, unrolled, drop every
+// addition of such a zero (a zonal launch takes the least of 8, 16, 32 and
+// 64 that holds r).
+template <typename S, int OP, bool STORE, bool SSE, int RB = 64>
 __device__ __forceinline__ void t64_group(const Args64& a, uint32_t b) {
     __shared__ __align__(16) int32_t lds[kTiles64 * kTile64];
     __shared__ long long red[kThreads64 / 64];
@@ -194,7 +198,8 @@ __device__ __forceinline__ void t64_group(const Args64& a, uint32_t b) {
         const bool kv = cv < a.r;
         const int lv = l64(cv);
 #pragma unroll
-        for (int u = 0; u < 64; ++u) Y[u] = (kv && u < a.r) ? (int32_t)((uint32_t)Y[u] << (12 - l64(u) - lv)) : 0;
+        for (int u = 0; u < 64; ++u)
+            Y[u] = (u < RB && kv && u < a.r) ? (int32_t)((uint32_t)Y[u] << (12 - l64(u) - lv)) : 0;
     } else {
         float fq[3], fd[3];
         column_factors64(a.qs, cv, fq);
@@ -226,7 +231,7 @@ __device__ __forceinline__ void t64_group(const Args64& a, uint32_t b) {
         int32_t c[64];
         const int32_t* l = lds + rt * kTile64 + rr * kRow64;
 #pragma unroll
-        for (int j = 0; j < 64; ++j) c[j] = l[j];
+        for (int j = 0; j < 64; ++j) c[j] = j < RB ? l[j] : 0;  // columns v >= RB are zero
         inv64(c, R);
     }
     constexpr int32_t lo = sizeof(S) == 1 ? 0 : -255, hi = 255;
@@ -266,9 +271,9 @@ __device__ __forceinline__ void t64_group(const Args64& a, uint32_t b) {
     }
 }
 
-template <typename S, int OP, bool STORE, bool SSE>
+template <typename S, int OP, bool STORE, bool SSE, int RB>
 __global__ __launch_bounds__(kThreads64) void k_t64(Args64 a) {
-    t64_group<S, OP, STORE, SSE>(a, blockIdx.x);
+    t64_group<S, OP, STORE, SSE, RB>(a, blockIdx.x);
 }
 
 // T64^T Y T64 per block (block-major int32 in and out).
@@ -342,13 +347,23 @@ uint32_t grid64(const Args64& a) {
     return a.spread_rows ? a.spread_rows * kSpread64 : (a.nblk + kTiles64 - 1) / kTiles64;
 }
 
-template <typename S, int OP, bool STORE>
-void launch64(const Args64& a, hipStream_t s) {
+template <typename S, int OP, bool STORE, int RB>
+void launch64_rb(const Args64& a, hipStream_t s) {
     const dim3 grid(grid64(a));
     if (a.sse)
-        hipLaunchKernelGGL((k_t64<S, OP, STORE, true>), grid, dim3(kThreads64), 0, s, a);
+        hipLaunchKernelGGL((k_t64<S, OP, STORE, true, RB>), grid, dim3(kThreads64), 0, s, a);
     else
-        hipLaunchKernelGGL((k_t64<S, OP, STORE, false>), grid, dim3(kThreads64), 0, s, a);
+        hipLaunchKernelGGL((k_t64<S, OP, STORE, false, RB>), grid, dim3(kThreads64), 0, s, a);
+}
+
+template <typename S, int OP, bool STORE>
+void launch64(const Args64& a, hipStream_t s) {
+    if constexpr (OP == kZonal64) {
+        if (a.r <= 8) return launch64_rb<S, OP, STORE, 8>(a, s);
+        if (a.r <= 16) return launch64_rb<S, OP, STORE, 16>(a, s);
+        if (a.r <= 32) return launch64_rb<S, OP, STORE, 32>(a, s);
+    }
+    launch64_rb<S, OP, STORE, 64>(a, s);
 }
 
 template <int OP>
