@@ -7,14 +7,14 @@
 // separable.  A workgroup computes a tile of 16 x 48 positions from a
 // 26 x 58 patch of both images (loaded as aligned 16-byte words):
 //   horizontal pass: each thread takes one patch row and four adjacent
-//     positions, holding the 14 samples they need in registers; the window
-//     is symmetric, so the five weighted sums (x, y, x^2, y^2, xy) are
-//     formed from exact integer sums of sample pairs, six multiply-adds
-//     each in float64, and go to LDS;
+//     positions; the 14 samples they need are converted to float64 once
+//     and their products formed once (exact), and the five weighted sums
+//     (x, y, x^2, y^2, xy) take 11 multiply-adds per position, two
+//     quantities' chains interleaved, and go to LDS;
 //   vertical pass: each thread takes three positions of one column, reading
 //     the 13 rows they need once per quantity.
-// Everything after the integer pair sums is float64: the variances are
-// differences of nearly equal moments.
+// All of it is float64: the variances are differences of nearly equal
+// moments.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -56,6 +56,45 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
     return v;
 }
 
+// The 11-tap weighted sums of kHW adjacent positions over values v (one
+// quantity), as kHW independent chains, written to out[0 .. kHW - 1].
+template <int N>
+__device__ __forceinline__ void taps1(const double (&w)[kWin], const double (&v)[N], double* out) {
+    double acc[kHW];
+#pragma unroll
+    for (int m = 0; m < kHW; ++m) acc[m] = w[0] * v[m];
+#pragma unroll
+    for (int k = 1; k < kWin; ++k)
+#pragma unroll
+        for (int m = 0; m < kHW; ++m) acc[m] = fma(w[k], v[m + k], acc[m]);
+#pragma unroll
+    for (int m = 0; m < kHW; ++m) out[m] = acc[m];
+}
+
+// The same for two quantities at once (2 kHW chains).
+template <int N>
+__device__ __forceinline__ void taps2(const double (&w)[kWin], const double (&u)[N], const double (&v)[N],
+                                      double* out_u, double* out_v) {
+    double au[kHW], av[kHW];
+#pragma unroll
+    for (int m = 0; m < kHW; ++m) {
+        au[m] = w[0] * u[m];
+        av[m] = w[0] * v[m];
+    }
+#pragma unroll
+    for (int k = 1; k < kWin; ++k)
+#pragma unroll
+        for (int m = 0; m < kHW; ++m) {
+            au[m] = fma(w[k], u[m + k], au[m]);
+            av[m] = fma(w[k], v[m + k], av[m]);
+        }
+#pragma unroll
+    for (int m = 0; m < kHW; ++m) {
+        out_u[m] = au[m];
+        out_v[m] = av[m];
+    }
+}
+
 // 40 KB of LDS and at most 128 VGPRs: four workgroups per CU.
 __global__ __launch_bounds__(256) void k_ssim(SsimArgs s) {
     __shared__ uint4 pa[kPH][2], pb[kPH][2];  // patch rows as two 16-byte words (26 of 32 bytes used)
@@ -87,44 +126,32 @@ __global__ __launch_bounds__(256) void k_ssim(SsimArgs s) {
         for (int hw = tid; hw < kPH * (kTW / kHW); hw += 256) {
             // horizontal pass: patch row r, positions j0 .. j0 + 3
             const int r = hw / (kTW / kHW), j0 = (hw % (kTW / kHW)) * kHW;
-            int32_t xa[kHW + kWin - 1], xb[kHW + kWin - 1];
+            constexpr int kS = kHW + kWin - 1;
+            double da[kS], db[kS];
             const uint8_t* ra = reinterpret_cast<const uint8_t*>(pa[r]);
             const uint8_t* rb = reinterpret_cast<const uint8_t*>(pb[r]);
 #pragma unroll
-            for (int c = 0; c < kHW + kWin - 1; ++c) {
-                xa[c] = ra[j0 + c];
-                xb[c] = rb[j0 + c];
+            for (int c = 0; c < kS; ++c) {
+                da[c] = (double)ra[j0 + c];
+                db[c] = (double)rb[j0 + c];
+            }
+            double* out = &h[0][r][j0];
+            constexpr int kQ = kPH * kLdh;  // LDS stride between the quantities (doubles)
+            // x and y, then xy, then x^2 and y^2 (squared in place): eight or
+            // four independent chains of 11 multiply-adds at a time
+            taps2<kS>(s.w, da, db, out, out + kQ);
+            {
+                double p[kS];
+#pragma unroll
+                for (int c = 0; c < kS; ++c) p[c] = da[c] * db[c];
+                taps1<kS>(s.w, p, out + 4 * kQ);
             }
 #pragma unroll
-            for (int m = 0; m < kHW; ++m) {
-                double acc[5];
-                // centre tap
-                {
-                    const int32_t a = xa[m + 5], b = xb[m + 5];
-                    const double w = s.w[5];
-                    acc[0] = w * (double)a;
-                    acc[1] = w * (double)b;
-                    acc[2] = w * (double)(a * a);
-                    acc[3] = w * (double)(b * b);
-                    acc[4] = w * (double)(a * b);
-                }
-                // taps k and 10 - k share a weight: exact integer pair sums
-#pragma unroll
-                for (int k = 0; k < 5; ++k) {
-                    const int32_t a0 = xa[m + k], a1 = xa[m + kWin - 1 - k];
-                    const int32_t b0 = xb[m + k], b1 = xb[m + kWin - 1 - k];
-                    const double w = s.w[k];
-                    acc[0] = fma(w, (double)(a0 + a1), acc[0]);
-                    acc[1] = fma(w, (double)(b0 + b1), acc[1]);
-                    acc[2] = fma(w, (double)(a0 * a0 + a1 * a1), acc[2]);
-                    acc[3] = fma(w, (double)(b0 * b0 + b1 * b1), acc[3]);
-                    acc[4] = fma(w, (double)(a0 * b0 + a1 * b1), acc[4]);
-                }
-#pragma unroll
-                for (int q = 0; q < 5; ++q) h[q][r][j0 + m] = acc[q];
-                // keeps the four positions' work from being interleaved (registers)
-                __builtin_amdgcn_sched_barrier(0);
+            for (int c = 0; c < kS; ++c) {
+                da[c] *= da[c];
+                db[c] *= db[c];
             }
+            taps2<kS>(s.w, da, db, out + 2 * kQ, out + 3 * kQ);
         }
         __syncthreads();
         // vertical pass: column j, positions i0 .. i0 + 2
@@ -140,10 +167,13 @@ __global__ __launch_bounds__(256) void k_ssim(SsimArgs s) {
                 double v = s.w[0] * col[m];
 #pragma unroll
                 for (int k = 1; k < kWin; ++k) v = fma(s.w[k], col[m + k], v);
+                // pinned here: the sums are formed now, so that this
+                // quantity's column is dead before the next one is read
+                // (otherwise every quantity's reads are hoisted ahead and
+                // held in registers at once)
+                __asm__ volatile("" : "+v"(v));
                 st[q][m] = v;
             }
-            // one quantity's column at a time (registers)
-            __builtin_amdgcn_sched_barrier(0);
         }
         double v = 0.0;
 #pragma unroll
