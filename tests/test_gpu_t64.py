@@ -72,7 +72,9 @@ def test_t64_pitched_plane():
     assert int((out_buf[:, :128] != 7).sum().item()) == 0 and int((out_buf[:, 320:] != 7).sum().item()) == 0
 
 
-@pytest.mark.parametrize("r", [0, 1, 2, 5, 8, 16, 33, 63, 64])
+# a zonal launch takes a compile-time bound on r (8, 16, 32 or 64): both
+# ends of every class are here
+@pytest.mark.parametrize("r", [0, 1, 2, 5, 8, 9, 16, 17, 32, 33, 63, 64])
 @pytest.mark.parametrize("store", [True, False])
 @pytest.mark.parametrize("shape,image_h", [((192, 320), 192), ((384, 128), 128), ((512, 256), 64), ((64, 64), 64)])
 def test_t64_encode_zonal(r, store, shape, image_h):
