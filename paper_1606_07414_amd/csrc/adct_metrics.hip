@@ -20,6 +20,7 @@
 #include <cmath>
 
 #include "adct_internal.hpp"
+#include "adct_tile.hpp"
 
 namespace adct {
 namespace {
@@ -44,7 +45,8 @@ struct SsimArgs {
     int64_t pitch_a, pitch_b;
     uint32_t width, image_height;
     uint32_t tiles_x, tiles_y;       // position tiles per image row / column
-    uint64_t units;                  // images * tiles_y * tiles_x
+    uint32_t units;                  // images * tiles_y * tiles_x (below 2^31)
+    FastDiv per_image_div, tiles_x_div;  // / (tiles_y * tiles_x), / tiles_x
     double w[kWin];                  // 1D Gaussian weights (outer product = window)
     double c1, c2;
     double* sum;                     // per image: sum of SSIM over positions
@@ -103,9 +105,12 @@ __global__ __launch_bounds__(256) void k_ssim(SsimArgs s) {
     const int tid = threadIdx.x;
     const uint32_t per_image = s.tiles_x * s.tiles_y;
     const uint32_t valid_h = s.image_height - (kWin - 1), valid_w = s.width - (kWin - 1);
-    for (uint64_t unit = blockIdx.x; unit < s.units; unit += gridDim.x) {
-        const uint32_t img = (uint32_t)(unit / per_image), rem = (uint32_t)(unit % per_image);
-        const uint32_t oy = (rem / s.tiles_x) * kTH, ox = (rem % s.tiles_x) * kTW;
+    for (uint32_t unit = blockIdx.x; unit < s.units; unit += gridDim.x) {
+        // the tile's image and place: uniform, by multiply-high (no division
+        // sequence on the vector unit)
+        const uint32_t img = fdiv(unit, s.per_image_div), rem = unit - img * per_image;
+        const uint32_t ty = fdiv(rem, s.tiles_x_div), tx = rem - ty * s.tiles_x;
+        const uint32_t oy = ty * kTH, ox = tx * kTW;
         __syncthreads();  // the previous tile is done with LDS
         for (int t = tid; t < 4 * kPH; t += 256) {
             // one 16-byte word per step: row i, word k of image a or b.  ox
@@ -231,7 +236,11 @@ int adct_ssim(const adct_plane* a, const adct_plane* b, int32_t image_height, do
     const uint32_t vh = s.image_height - (kWin - 1), vw = s.width - (kWin - 1);
     s.tiles_x = (vw + kTW - 1) / kTW;
     s.tiles_y = (vh + kTH - 1) / kTH;
-    s.units = (uint64_t)nimg * s.tiles_x * s.tiles_y;
+    const uint64_t units = (uint64_t)nimg * s.tiles_x * s.tiles_y;
+    if (units > (uint64_t)INT32_MAX) return ADCT_E_TOO_LARGE;
+    s.units = (uint32_t)units;
+    s.per_image_div = make_fastdiv(s.tiles_x * s.tiles_y);
+    s.tiles_x_div = make_fastdiv(s.tiles_x);
     double g[kWin], gs = 0.0;
     for (int k = 0; k < kWin; ++k) {
         const double d = k - (kWin - 1) / 2.0;
@@ -244,7 +253,7 @@ int adct_ssim(const adct_plane* a, const adct_plane* b, int32_t image_height, do
     s.sum = ssim;
     hipLaunchKernelGGL(k_fill_f64, dim3((nimg + 255) / 256), dim3(256), 0, st, ssim, nimg, 0.0);
     if ((rc = launched())) return rc;
-    const uint64_t grid = s.units < 262144 ? s.units : 262144;
+    const uint32_t grid = s.units < 262144u ? s.units : 262144u;
     hipLaunchKernelGGL(k_ssim, dim3((unsigned)grid), dim3(256), 0, st, s);
     if ((rc = launched())) return rc;
     hipLaunchKernelGGL(k_scale_f64, dim3((nimg + 255) / 256), dim3(256), 0, st, ssim, nimg,
