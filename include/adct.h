@@ -478,7 +478,8 @@ int adct_mixed_encode(const adct_plane* src, int qp, int64_t lambda, int16_t* q,
  * of `image_height` rows (a multiple of 16 dividing the height).
  * ssim: device float64 [height / image_height], 8-byte aligned, overwritten.
  * Computed in float64; the summation order over positions is not fixed, so
- * repeated calls agree to about 1e-15 relative. */
+ * repeated calls agree to about 1e-15 relative.  ADCT_E_TOO_LARGE when the
+ * planes hold more than 2^31 - 1 tiles of 16 x 48 positions. */
 int adct_ssim(const adct_plane* a, const adct_plane* b, int32_t image_height, double* ssim, void* stream);
 
 /* ---- uneven batches: one persistent launch over a device work queue -- */
