@@ -45,7 +45,15 @@ struct Args32 {
     Scale5 qs, dqs;          // per class c = log2 d_u + log2 d_v - 6
     unsigned long long* sse; // per image, or null
     uint32_t spread_rows;    // 0: workgroup b takes group b; else interleaved (see k_t32)
+    bool sat;                // quantising: levels may leave int16 and are saturated (host side)
 };
+
+// Whether the levels of a 32x32 quantising call can leave int16.  A level is
+// at most sqrt(d_u d_v) |x|max / Delta <= 32 |x|max / Delta (entries of T32
+// in {0, +1, -1}, d_u of them nonzero in row u): for uint8 samples 8160 /
+// Delta, within int16 at every QP; for int16 samples within +-2047 it is
+// 65504 / Delta, within int16 from QP 10 (Delta = 2) on.
+bool levels_may_saturate32(int32_t dtype, int qp) { return dtype != ADCT_U8 && qp < 10; }
 
 constexpr int kTiles32 = 8;                // tiles per workgroup
 constexpr int kRow32 = 33;                 // LDS words per staged row
@@ -144,8 +152,9 @@ __device__ __forceinline__ void column_factors32(const Scale5& t, int v, float (
 // the zonal size at compile time (r <= RB): the coefficients with u or v >=
 // RB are then known zeros, and the inverse passes, unrolled, drop every
 // addition of such a zero (a zonal launch takes the least of 8, 16 and 32
-// that holds r).
-template <typename S, int OP, bool STORE, bool SSE, int RB = 32>
+// that holds r).  SAT: the quantiser saturates its levels to int16 (the
+// host leaves it out where they provably fit).
+template <typename S, int OP, bool STORE, bool SSE, int RB = 32, bool SAT = true>
 __device__ __forceinline__ void t32_group(const Args32& a, uint32_t b) {
     __shared__ __align__(16) int32_t lds[kTiles32 * kTile32];
     __shared__ long long red[4];
@@ -207,7 +216,8 @@ __device__ __forceinline__ void t32_group(const Args32& a, uint32_t b) {
         int16_t* o = static_cast<int16_t*>(a.cout) + (int64_t)cg * 1024 + cv;
 #pragma unroll
         for (int u = 0; u < 32; ++u) {
-            const int32_t q = clamp_i32(round_away(__fmul_rn((float)Y[u], fq[l32(u) - 3])), -32768, 32767);
+            const int32_t q0 = round_away(__fmul_rn((float)Y[u], fq[l32(u) - 3]));
+            const int32_t q = SAT ? clamp_i32(q0, -32768, 32767) : q0;
             if constexpr (STORE) {
                 if (cok) o[u * 32] = (int16_t)q;
             }
@@ -275,9 +285,9 @@ __device__ __forceinline__ void t32_group(const Args32& a, uint32_t b) {
 constexpr int kInvRow = 36;                     // output staging: words per row
 constexpr int kInvTile = 32 * kInvRow + 4;      // and per tile
 
-template <typename S, int OP, bool STORE, bool SSE, int RB>
+template <typename S, int OP, bool STORE, bool SSE, int RB, bool SAT>
 __global__ __launch_bounds__(256) void k_t32(Args32 a) {
-    t32_group<S, OP, STORE, SSE, RB>(a, blockIdx.x);
+    t32_group<S, OP, STORE, SSE, RB, SAT>(a, blockIdx.x);
 }
 
 // Several planes in one launch: plane i takes the workgroups from first[i]
@@ -288,13 +298,13 @@ struct Set32 {
     uint32_t n;
 };
 
-template <typename S, int OP, bool STORE, bool SSE>
+template <typename S, int OP, bool STORE, bool SSE, bool SAT>
 __global__ __launch_bounds__(256) void k_t32_planes(Set32 ps) {
     uint32_t i = 0;
 #pragma unroll
     for (uint32_t k = 1; k < (uint32_t)ADCT_MAX_PLANES; ++k)
         if (k < ps.n && blockIdx.x >= ps.first[k]) i = k;
-    t32_group<S, OP, STORE, SSE>(ps.p[i], blockIdx.x - ps.first[i]);
+    t32_group<S, OP, STORE, SSE, 32, SAT>(ps.p[i], blockIdx.x - ps.first[i]);
 }
 
 __global__ __launch_bounds__(256) void k_t32_inv(const int32_t* __restrict__ in, int32_t* __restrict__ out,
@@ -364,13 +374,13 @@ uint32_t grid32(const Args32& a) {
     return a.spread_rows ? a.spread_rows * kSpread32 : (a.nblk + kTiles32 - 1) / kTiles32;
 }
 
-template <typename S, int OP, bool STORE, int RB>
+template <typename S, int OP, bool STORE, int RB, bool SAT = true>
 void launch32_rb(const Args32& a, hipStream_t s) {
     const dim3 grid(grid32(a));
     if (a.sse)
-        hipLaunchKernelGGL((k_t32<S, OP, STORE, true, RB>), grid, dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_t32<S, OP, STORE, true, RB, SAT>), grid, dim3(256), 0, s, a);
     else
-        hipLaunchKernelGGL((k_t32<S, OP, STORE, false, RB>), grid, dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_t32<S, OP, STORE, false, RB, SAT>), grid, dim3(256), 0, s, a);
 }
 
 template <typename S, int OP, bool STORE>
@@ -378,6 +388,9 @@ void launch32(const Args32& a, hipStream_t s) {
     if constexpr (OP == kZonal32) {
         if (a.r <= 8) return launch32_rb<S, OP, STORE, 8>(a, s);
         if (a.r <= 16) return launch32_rb<S, OP, STORE, 16>(a, s);
+    }
+    if constexpr (OP == kQuant32) {
+        if (!a.sat) return launch32_rb<S, OP, STORE, 32, false>(a, s);
     }
     launch32_rb<S, OP, STORE, 32>(a, s);
 }
@@ -438,7 +451,11 @@ int setup32(const adct_plane* src, void* coef, const adct_plane* dst, int32_t im
 
 template <typename S, bool STORE, bool SSE>
 void launch32_planes(const Set32& ps, uint32_t grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_t32_planes<S, kQuant32, STORE, SSE>), dim3(grid), dim3(256), 0, s, ps);
+    // every plane of the set has the same sample type and QP
+    if (ps.p[0].sat)
+        hipLaunchKernelGGL((k_t32_planes<S, kQuant32, STORE, SSE, true>), dim3(grid), dim3(256), 0, s, ps);
+    else
+        hipLaunchKernelGGL((k_t32_planes<S, kQuant32, STORE, SSE, false>), dim3(grid), dim3(256), 0, s, ps);
 }
 
 template <typename S>
@@ -470,6 +487,7 @@ int t32_encode_quant_planes(const adct_quant_job* jobs, int32_t njobs, int qp, v
             a.qs.f[c] = qs[c];
             a.dqs.f[c] = dqs[c];
         }
+        a.sat = levels_may_saturate32(dt, qp);
         ps.first[i] = (uint32_t)grid;
         grid += grid32(a);
         if (want_sse) {
@@ -541,6 +559,7 @@ int adct_t32_encode_quant(const adct_plane* src, int qp, int16_t* q, const adct_
         a.qs.f[c] = qs[c];
         a.dqs.f[c] = dqs[c];
     }
+    a.sat = levels_may_saturate32(src->dtype, qp);
     return launch32_typed<kQuant32>(src->dtype, a, s);
 }
 

@@ -48,7 +48,15 @@ struct Args64 {
     Scale5 qs, dqs;          // per class c = log2 d_u + log2 d_v - 8
     unsigned long long* sse; // per image, or null
     uint32_t spread_rows;    // 0: workgroup b takes group b; else interleaved (see t64_group)
+    bool sat;                // quantising: levels may leave int16 and are saturated (host side)
 };
+
+// Whether the levels of a 64x64 quantising call can leave int16.  A level is
+// at most sqrt(d_u d_v) |x|max / Delta <= 64 |x|max / Delta (entries of T64
+// in {0, +1, -1}, d_u of them nonzero in row u): for uint8 samples 16320 /
+// Delta, within int16 at every QP (Delta >= 0.63); for int16 samples within
+// +-2047 it is 131008 / Delta, within int16 from QP 16 (Delta = 4) on.
+bool levels_may_saturate64(int32_t dtype, int qp) { return dtype != ADCT_U8 && qp < 16; }
 
 constexpr int kTiles64 = 2;                 // tiles per workgroup
 constexpr int kThreads64 = 64 * kTiles64;   // threads per workgroup
@@ -144,8 +152,9 @@ __device__ __forceinline__ void column_factors64(const Scale5& t, int v, float (
 // the zonal size at compile time (r <= RB): the coefficients with u or v >=
 // RB are then known zeros, and the inverse passes, unrolled, drop every
 // addition of such a zero (a zonal launch takes the least of 8, 16, 32 and
-// 64 that holds r).
-template <typename S, int OP, bool STORE, bool SSE, int RB = 64>
+// 64 that holds r).  SAT: the quantiser saturates its levels to int16 (the
+// host leaves it out where they provably fit).
+template <typename S, int OP, bool STORE, bool SSE, int RB = 64, bool SAT = true>
 __device__ __forceinline__ void t64_group(const Args64& a, uint32_t b) {
     __shared__ __align__(16) int32_t lds[kTiles64 * kTile64];
     __shared__ long long red[kThreads64 / 64];
@@ -207,7 +216,8 @@ __device__ __forceinline__ void t64_group(const Args64& a, uint32_t b) {
         int16_t* o = static_cast<int16_t*>(a.cout) + (int64_t)cg * 4096 + cv;
 #pragma unroll
         for (int u = 0; u < 64; ++u) {
-            const int32_t q = clamp_i32(round_away(__fmul_rn((float)Y[u], fq[l64(u) - 4])), -32768, 32767);
+            const int32_t q0 = round_away(__fmul_rn((float)Y[u], fq[l64(u) - 4]));
+            const int32_t q = SAT ? clamp_i32(q0, -32768, 32767) : q0;
             if constexpr (STORE) {
                 if (cok) o[u * 64] = (int16_t)q;
             }
@@ -271,9 +281,9 @@ __device__ __forceinline__ void t64_group(const Args64& a, uint32_t b) {
     }
 }
 
-template <typename S, int OP, bool STORE, bool SSE, int RB>
+template <typename S, int OP, bool STORE, bool SSE, int RB, bool SAT>
 __global__ __launch_bounds__(kThreads64) void k_t64(Args64 a) {
-    t64_group<S, OP, STORE, SSE, RB>(a, blockIdx.x);
+    t64_group<S, OP, STORE, SSE, RB, SAT>(a, blockIdx.x);
 }
 
 // T64^T Y T64 per block (block-major int32 in and out).
@@ -347,13 +357,13 @@ uint32_t grid64(const Args64& a) {
     return a.spread_rows ? a.spread_rows * kSpread64 : (a.nblk + kTiles64 - 1) / kTiles64;
 }
 
-template <typename S, int OP, bool STORE, int RB>
+template <typename S, int OP, bool STORE, int RB, bool SAT = true>
 void launch64_rb(const Args64& a, hipStream_t s) {
     const dim3 grid(grid64(a));
     if (a.sse)
-        hipLaunchKernelGGL((k_t64<S, OP, STORE, true, RB>), grid, dim3(kThreads64), 0, s, a);
+        hipLaunchKernelGGL((k_t64<S, OP, STORE, true, RB, SAT>), grid, dim3(kThreads64), 0, s, a);
     else
-        hipLaunchKernelGGL((k_t64<S, OP, STORE, false, RB>), grid, dim3(kThreads64), 0, s, a);
+        hipLaunchKernelGGL((k_t64<S, OP, STORE, false, RB, SAT>), grid, dim3(kThreads64), 0, s, a);
 }
 
 template <typename S, int OP, bool STORE>
@@ -362,6 +372,9 @@ void launch64(const Args64& a, hipStream_t s) {
         if (a.r <= 8) return launch64_rb<S, OP, STORE, 8>(a, s);
         if (a.r <= 16) return launch64_rb<S, OP, STORE, 16>(a, s);
         if (a.r <= 32) return launch64_rb<S, OP, STORE, 32>(a, s);
+    }
+    if constexpr (OP == kQuant64) {
+        if (!a.sat) return launch64_rb<S, OP, STORE, 64, false>(a, s);
     }
     launch64_rb<S, OP, STORE, 64>(a, s);
 }
@@ -464,6 +477,7 @@ int adct_t64_encode_quant(const adct_plane* src, int qp, int16_t* q, const adct_
         a.qs.f[c] = qs[c];
         a.dqs.f[c] = dqs[c];
     }
+    a.sat = levels_may_saturate64(src->dtype, qp);
     return launch64_typed<kQuant64>(src->dtype, a, s);
 }
 
