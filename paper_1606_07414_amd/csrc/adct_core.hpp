@@ -744,13 +744,18 @@ constexpr int kTPW = ADCT_TPW;
 static_assert(kTPW >= 8 && (kTPW & (kTPW - 1)) == 0, "TPW must be a power of two >= 8");
 
 #ifndef ADCT_SSE_SPREAD
-#define ADCT_SSE_SPREAD 256
+#define ADCT_SSE_SPREAD 4
 #endif
 // Workgroups of a launch that accumulates per-image SSE over large images
 // (more than kSseSpreadMin chunks per image) are dealt over the plane in
 // kSseSpread interleaved streams, so that the workgroups resident at one
-// time work on (and add to the SSE of) many different images instead of
-// queueing on the atomics of a few.
+// time add to the SSE of several images instead of queueing on the atomics
+// of one or two.  Few streams suffice for that, and each stream stays a
+// sequential sweep of its part of the plane: with 256 streams the
+// resident workgroups touched 256 places at once and a 25.8 GB launch
+// streamed 4.2 TB/s; 16, 8, 4 and 2 streams gave 5.55, 5.77, 5.84 and
+// 5.74 TB/s (no interleave 5.65), and 2 streams let the video frames'
+// atomics queue again.
 #ifndef ADCT_SSE_SPREAD_MIN
 #define ADCT_SSE_SPREAD_MIN 64
 #endif

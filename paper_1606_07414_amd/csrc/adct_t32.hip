@@ -60,9 +60,10 @@ constexpr int kRow32 = 33;                 // LDS words per staged row
 constexpr int kTile32 = 32 * kRow32 + 4;   // LDS words per staged tile
 // Workgroups of a launch that adds to the SSE of large images are dealt
 // over the plane in this many interleaved streams (as the 16-point group
-// kernel does), so that the workgroups resident at one time add to many
-// images' sums instead of queueing on the atomics of a few.
-constexpr uint32_t kSpread32 = 256;
+// kernel does), so that the workgroups resident at one time add to several
+// images' sums instead of queueing on the atomics of one, while each stream
+// stays a sequential sweep of its part of the plane.
+constexpr uint32_t kSpread32 = 4;
 constexpr uint32_t kSpreadMin32 = 64;      // groups of 8 tiles per image
 
 // Raw words of one 32-sample row (uint8: 8 words, int16: 16) and their

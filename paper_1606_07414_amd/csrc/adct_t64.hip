@@ -64,9 +64,10 @@ constexpr int kRow64 = 65;                  // LDS words per staged row
 constexpr int kTile64 = 64 * kRow64 + 8;    // LDS words per staged tile
 // Workgroups of a launch that adds to the SSE of large images are dealt
 // over the plane in this many interleaved streams (as the 16-point group
-// kernel does), so that the workgroups resident at one time add to many
-// images' sums instead of queueing on the atomics of a few.
-constexpr uint32_t kSpread64 = 256;
+// kernel does), so that the workgroups resident at one time add to several
+// images' sums instead of queueing on the atomics of one, while each stream
+// stays a sequential sweep of its part of the plane.
+constexpr uint32_t kSpread64 = 4;
 constexpr uint32_t kSpreadMin64 = 16;       // groups of 2 tiles per image
 
 // Raw words of one 64-sample row (uint8: 16 words, int16: 32).
