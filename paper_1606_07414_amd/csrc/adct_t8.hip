@@ -44,9 +44,10 @@ struct Args8 {
 
 // Workgroups of a launch that adds to the SSE of large images are dealt
 // over the plane in this many interleaved streams (as the 16-point group
-// kernel does), so that the workgroups resident at one time add to many
-// images' sums instead of queueing on the atomics of a few.
-constexpr uint32_t kSpread8 = 256;
+// kernel does), so that the workgroups resident at one time add to several
+// images' sums instead of queueing on the atomics of one, while each stream
+// stays a sequential sweep of its part of the plane.
+constexpr uint32_t kSpread8 = 4;
 constexpr uint32_t kSpreadMin8 = 16;  // chunks of 256 blocks per image
 
 // One block row as raw words (uint8: 8 samples in w.x, w.y; int16: 8
