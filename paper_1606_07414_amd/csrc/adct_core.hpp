@@ -451,7 +451,7 @@ __device__ __forceinline__ void store_row_fixed(char* p, const int32_t (&o)[16])
             const uint32_t hi = perm((uint32_t)o[4 * k + 3], (uint32_t)o[4 * k + 2], 0x05010c0cu);
             ws[k] = lo | hi;
         }
-        store16(p, make_uint4(ws[0], ws[1], ws[2], ws[3]));
+        store16_rowpiece(p, make_uint4(ws[0], ws[1], ws[2], ws[3]));
     } else {
         uint32_t ws[8];
 #pragma unroll
