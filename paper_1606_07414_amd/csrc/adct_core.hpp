@@ -440,9 +440,12 @@ __device__ __forceinline__ uint32_t pack_fixed_pair(int32_t a, int32_t b) {
         return perm((uint32_t)b, (uint32_t)a, 0x06050201u);
 }
 
-// Stores the 16 samples of a row of out_fixed values.
+// Stores the 16 samples of a row of out_fixed values.  `shared_lines`
+// (uint8 planes): the plane's tile-group row segments begin or end inside
+// 128-byte lines, which neighbouring groups then also write (see
+// store16_rowpiece).
 template <typename S>
-__device__ __forceinline__ void store_row_fixed(char* p, const int32_t (&o)[16]) {
+__device__ __forceinline__ void store_row_fixed(char* p, const int32_t (&o)[16], bool shared_lines = false) {
     if constexpr (sizeof(S) == 1) {
         uint32_t ws[4];
 #pragma unroll
@@ -451,7 +454,10 @@ __device__ __forceinline__ void store_row_fixed(char* p, const int32_t (&o)[16])
             const uint32_t hi = perm((uint32_t)o[4 * k + 3], (uint32_t)o[4 * k + 2], 0x05010c0cu);
             ws[k] = lo | hi;
         }
-        store16_rowpiece(p, make_uint4(ws[0], ws[1], ws[2], ws[3]));
+        if (shared_lines)
+            store16_rowpiece(p, make_uint4(ws[0], ws[1], ws[2], ws[3]));
+        else
+            store16(p, make_uint4(ws[0], ws[1], ws[2], ws[3]));
     } else {
         uint32_t ws[8];
 #pragma unroll
@@ -690,10 +696,14 @@ __device__ __forceinline__ void process_group(const GroupArgs& a, uint32_t g0, u
         if constexpr (sizeof(S) == 1) {
             // one 16-byte piece per row: the lanes of a sample row store one
             // contiguous run
+            // groups of whole lines (base, pitch and row length multiples of
+            // 128 bytes) keep the streaming stores, which leave the cache to
+            // inputs that a later call may read again
+            const bool shared_lines = (((uintptr_t)a.dst.data | (uint64_t)a.dst.pitch | (uint64_t)(a.bw * 16u)) & 127u) != 0;
             if (rok) {
                 char* pa = const_cast<char*>(row_ptr<S>(a.dst, rby, rbx, rip));
-                store_row_fixed<S>(pa, r0);
-                store_row_fixed<S>(pa + 8 * a.dst.pitch, r1);
+                store_row_fixed<S>(pa, r0, shared_lines);
+                store_row_fixed<S>(pa + 8 * a.dst.pitch, r1, shared_lines);
             }
         } else {
             __syncthreads();  // every read of the inverse transpose is done

@@ -24,12 +24,14 @@ __device__ __forceinline__ void store16(void* p, uint4 w) {
 }
 
 // 16-byte store of a row piece of a sample plane written straight from the
-// row role: through the cache.  When the plane's pitch is not a multiple of
-// 128 bytes, every tile group's row segment starts and ends inside a line
-// that the neighbouring group also writes; the cache merges the two parts,
-// where nontemporal stores leave both partial.  Measured on the uneven
-// 4096-image batch (most widths not multiples of 128): 5.13 -> 5.63 TB/s;
-// on aligned rows the two forms tie.
+// row role, through the cache, for planes whose tile-group row segments
+// begin or end inside 128-byte lines (a pitch, base or row length that is
+// not a multiple of 128 bytes): the neighbouring group writes the rest of
+// such a line, and the cache merges the two parts where nontemporal stores
+// leave both partial.  Measured on the uneven 4096-image batch (most widths
+// not multiples of 128): 5.13 -> 5.63 TB/s.  Planes of whole lines keep the
+// nontemporal stores: there the two forms tie, and cached output would push
+// out of the Infinity Cache the inputs that a later call reads again.
 __device__ __forceinline__ void store16_rowpiece(void* p, uint4 w) { *static_cast<uint4*>(p) = w; }
 
 // ---- sample rows --------------------------------------------------------
