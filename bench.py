@@ -115,9 +115,21 @@ def copy_probe(torch, stream):
     return {"bytes_per_copy": 2 * COPY_PROBE_BYTES, "ms": ms, "gbs": 2 * COPY_PROBE_BYTES / (ms * 1e-3) / 1e9}
 
 
+WARM_MS = 30.0  # untimed calls before each timed leg measurement, in ms of wall time
+
+
 def timed(torch, fn, reps, stream):
-    """Average ms of `reps` back-to-back calls of fn, HIP events on `stream`."""
+    """Average ms of `reps` back-to-back calls of fn, HIP events on `stream`.
+    Untimed calls run first for WARM_MS: a leg starts after host-side data
+    preparation that leaves the GPU idle, and one call is too short to bring
+    its clocks back up (the first QPs of the video leg measured up to 20 %
+    slow after a single warm-up call)."""
     fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while (time.perf_counter() - t0) * 1e3 < WARM_MS:
+        fn()
+        torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(reps):
