@@ -64,27 +64,42 @@ int check_recon(const adct_plane* dst, const adct_plane* ref, int32_t image_heig
 // workgroup; launches that add to the SSE of large images interleave their
 // chunks.
 struct GroupGrid {
-    uint32_t gpw, rows, grid;
+    uint32_t gpw, rows, log2, grid;
 };
-GroupGrid group_grid(uint32_t nblk, bool sse, uint32_t image_tiles) {
+constexpr uint32_t log2_pow2(uint32_t n) { return n <= 1 ? 0 : 1 + log2_pow2(n >> 1); }
+
+// `shared_lines`: the launch writes uint8 rows whose tile-group segments
+// share lines with their neighbours' (kXcdRegions regions, see there).
+GroupGrid group_grid(uint32_t nblk, bool sse, uint32_t image_tiles, bool shared_lines = false) {
     GroupGrid g;
     g.gpw = groups_per_wg(nblk);
     const uint32_t span = g.gpw * (uint32_t)kTPW;
     const uint32_t chunks = (nblk + span - 1) / span;
-    const bool spread = sse && image_tiles / span > kSseSpreadMin;
-    g.rows = spread ? (chunks + kSseSpread - 1) / kSseSpread : 0u;
-    g.grid = g.rows ? g.rows * kSseSpread : chunks;
+    const uint32_t n = shared_lines ? kXcdRegions : kSseSpread;
+    const bool spread = shared_lines || (sse && image_tiles / span > kSseSpreadMin);
+    g.log2 = log2_pow2(n);
+    g.rows = spread ? (chunks + n - 1) / n : 0u;
+    g.grid = g.rows ? g.rows * n : chunks;
     return g;
+}
+
+// Host side of shares_lines for a launch's output plane.
+template <typename S, typename M>
+bool output_shares_lines(const GroupArgs& a) {
+    if (M::OUT != kOutSamples || sizeof(S) != 1) return false;
+    return (((uintptr_t)a.dst.data | (uint64_t)a.dst.pitch | (uint64_t)a.bw * 16u) & 127u) != 0;
 }
 
 template <typename S, typename M>
 int launch_group(uint32_t nblk, hipStream_t s, const GroupArgs& a) {
     if (nblk == 0) return ADCT_OK;
-    const GroupGrid g = group_grid(nblk, M::SSE && a.sse, a.image_tiles);
+    const GroupGrid g = group_grid(nblk, M::SSE && a.sse, a.image_tiles, output_shares_lines<S, M>(a));
     if (g.gpw == 1)
-        hipLaunchKernelGGL((k_group<kTPW, S, M, false>), dim3(g.grid), dim3(kTPW * 8), 0, s, a, nblk, g.gpw, g.rows);
+        hipLaunchKernelGGL((k_group<kTPW, S, M, false>), dim3(g.grid), dim3(kTPW * 8), 0, s, a, nblk, g.gpw, g.rows,
+                           g.log2);
     else
-        hipLaunchKernelGGL((k_group<kTPW, S, M, true>), dim3(g.grid), dim3(kTPW * 8), 0, s, a, nblk, g.gpw, g.rows);
+        hipLaunchKernelGGL((k_group<kTPW, S, M, true>), dim3(g.grid), dim3(kTPW * 8), 0, s, a, nblk, g.gpw, g.rows,
+                           g.log2);
     return launched();
 }
 
@@ -493,10 +508,13 @@ int adct_encode_quant_planes(const adct_quant_job* jobs, int32_t njobs, int qp, 
         a.qs = to_dev(qs);
         a.dqs = to_dev(dqs);
         sse_fields(&j.dst, &j.src, j.image_height, j.sse, a);
-        const GroupGrid g = group_grid((uint32_t)nblk, want_sse, a.image_tiles);
+        const bool shared =
+            dt == ADCT_U8 && (((uintptr_t)a.dst.data | (uint64_t)a.dst.pitch | (uint64_t)a.bw * 16u) & 127u) != 0;
+        const GroupGrid g = group_grid((uint32_t)nblk, want_sse, a.image_tiles, shared);
         pl.nblk = (uint32_t)nblk;
         pl.gpw = g.gpw;
         pl.spread_rows = g.rows;
+        pl.spread_log2 = g.log2;
         pl.first_wg = (uint32_t)grid;
         grid += g.grid;
         pf = pf || g.gpw > 1;

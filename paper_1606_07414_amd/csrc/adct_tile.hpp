@@ -34,6 +34,24 @@ __device__ __forceinline__ void store16(void* p, uint4 w) {
 // out of the Infinity Cache the inputs that a later call reads again.
 __device__ __forceinline__ void store16_rowpiece(void* p, uint4 w) { *static_cast<uint4*>(p) = w; }
 
+// Whether the tile-group row segments of an output plane can begin or end
+// inside a 128-byte line: its base, pitch or row length (bytes) is not a
+// multiple of 128.  A group is a run of whole tiles in raster order whose
+// row segment is a multiple of 128 bytes long, so with all three multiples
+// of 128 every segment is whole lines.  Uniform over a launch's plane.
+__device__ __forceinline__ bool shares_lines(const void* base, int64_t pitch, uint64_t row_bytes) {
+    return (((uintptr_t)base | (uint64_t)pitch | row_bytes) & 127u) != 0;
+}
+
+// A 16-byte row piece: through the cache on planes whose segments share
+// lines with their neighbours', streamed past it otherwise.
+__device__ __forceinline__ void store16_row(void* p, uint4 w, bool shared) {
+    if (shared)
+        store16_rowpiece(p, w);
+    else
+        store16(p, w);
+}
+
 // ---- sample rows --------------------------------------------------------
 template <typename S>
 struct Samples;
