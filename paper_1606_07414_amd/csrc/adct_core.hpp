@@ -183,6 +183,7 @@ __device__ __forceinline__ int32_t pair_sse(const int32_t (&r0)[16], const int32
 // Raw sample words of rows ip and ip+8 of one tile (row role).
 struct RowWords {
     uint4 a0, a1, b0, b1;
+    uint4 z[8];  // zone words of a zonal reconstruction (prefetch_zone)
 };
 
 template <typename S, int XF>
@@ -548,10 +549,82 @@ __device__ __forceinline__ void load_group_rows(const GroupArgs& a, uint32_t g0,
     load_rows<S>(a.src, rby, rbx, (uint32_t)rlt < ntile, rip, w.a0, w.a1, w.b0, w.b1);
 }
 
-// `rows` holds this group's input rows (forward modes); once they are
-// consumed, the rows of the next group (tiles g0n .. g0n + ntn - 1 of the
-// plane of `an`, which may be another image's; ntn = 0 for none) are
-// requested into it, so their latency overlaps this group's remaining work.
+// ---- zonal reconstruction with a compile-time zone ------------------------------
+#ifndef ADCT_ZONE_MAX
+#define ADCT_ZONE_MAX 16
+#endif
+// A uint8 zonal reconstruction from coefficients whose zone r x r is fixed at
+// compile time reads, per tile, only the first ceil(r/4) 16-byte words of its
+// first r coefficient rows, and the reference rows for the SSE.  For small r
+// that is too little to keep the memory busy while the group's transforms
+// run, so these words are requested a group ahead, into the `rows` of the
+// group loop: reference rows in a0 / b0 (as load_rows leaves them for
+// uint8), coefficient words in z.
+template <typename S, typename M>
+constexpr bool prefetch_zone() {
+    return M::IN == kInY && M::MID == kMidZonal && M::ZR > 0 && M::ZR <= ADCT_ZONE_MAX && sizeof(S) == 1;
+}
+
+// Word i of a group's kept coefficient words: tile t, row u, word v4 of the
+// row (kCols4 words per row, r rows per tile).
+template <int ZR>
+struct ZoneWords {
+    static constexpr int kCols4 = (ZR + 3) / 4;
+    static constexpr int kPerTile = ZR * kCols4;
+    __device__ static void at(int i, int& t, int& u, int& v4) {
+        t = i / kPerTile;
+        const int rem = i - t * kPerTile;
+        u = rem / kCols4;
+        v4 = rem - u * kCols4;
+    }
+};
+
+template <int TPW, typename S, typename M>
+__device__ __forceinline__ void load_zone_words(const GroupArgs& a, uint32_t g0, uint32_t ntile, RowWords& w) {
+    using Z = ZoneWords<M::ZR>;
+    constexpr int kThreads = TPW * 8, kWords = TPW * Z::kPerTile;
+    static_assert(kWords <= 8 * kThreads, "at most eight words per thread");
+    const int tid = threadIdx.x;
+    const uint4* in = reinterpret_cast<const uint4*>(static_cast<const int32_t*>(a.cin) + (int64_t)g0 * 256);
+#pragma unroll
+    for (int k = 0; k < (kWords + kThreads - 1) / kThreads; ++k) {
+        const int i = tid + k * kThreads;
+        int t, u, v4;
+        Z::at(i, t, u, v4);
+        w.z[k] = make_uint4(0, 0, 0, 0);
+        if (i < kWords && (uint32_t)t < ntile) w.z[k] = in[t * 64 + u * 4 + v4];
+    }
+    if constexpr (M::SSE) {
+        const int rlt = tid % TPW, rip = tid / TPW;
+        const uint32_t rg = g0 + (uint32_t)rlt;
+        const uint32_t rby = fdiv(rg, a.bwdiv), rbx = rg - rby * a.bw;
+        uint4 unused0, unused1;  // uint8 rows fill a0 and b0 only
+        load_rows<S>(a.ref, rby, rbx, (uint32_t)rlt < ntile, rip, w.a0, unused0, w.b0, unused1);
+    }
+}
+
+// Writes the kept words into the group's LDS blocks.  The words outside the
+// zone are left as they are: the zonal weights zero every coefficient
+// outside r x r before it is used.
+template <int TPW, typename M>
+__device__ __forceinline__ void zone_words_to_lds(const RowWords& w, uint32_t* lds) {
+    using Z = ZoneWords<M::ZR>;
+    constexpr int kThreads = TPW * 8, kWords = TPW * Z::kPerTile;
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < (kWords + kThreads - 1) / kThreads; ++k) {
+        const int i = tid + k * kThreads;
+        int t, u, v4;
+        Z::at(i, t, u, v4);
+        if (i < kWords) *reinterpret_cast<uint4*>(lds + t * kIntTile + u * kIntRow + 4 * v4) = w.z[k];
+    }
+}
+
+// `rows` holds this group's input rows (forward modes) or its zone words
+// (prefetch_zone); once they are consumed, those of the next group (tiles
+// g0n .. g0n + ntn - 1 of the plane of `an`, which may be another image's;
+// ntn = 0 for none) are requested into it, so their latency overlaps this
+// group's remaining work.
 // `qs`, `dqs` must refer to kernel-argument or global memory: the per-class
 // selects in column_factors may be compiled into indexed loads.
 template <int TPW, typename S, typename M>
@@ -581,6 +654,16 @@ __device__ __forceinline__ void process_group(const GroupArgs& a, uint32_t g0, u
         if (ntn) load_group_rows<TPW, S>(an, g0n, ntn, rows);
         __syncthreads();
         fwd_columns<S, M::XF>(lds, clt, cp, ya, yb);
+    } else if constexpr (prefetch_zone<S, M>()) {
+        zone_words_to_lds<TPW, M>(rows, lds);
+        if constexpr (M::SSE) {
+            ra0 = rows.a0;
+            rb0 = rows.b0;
+            ra1 = rb1 = make_uint4(0, 0, 0, 0);
+        }
+        __syncthreads();
+        if (ntn) load_zone_words<TPW, S, M>(an, g0n, ntn, rows);
+        lds_get_columns(lds, clt, cp, ya, yb);
     } else {
         if constexpr (M::SSE) {
             // prefetch the reference rows so their latency overlaps the rest
@@ -798,6 +881,7 @@ __device__ __forceinline__ void group_chunk(const GroupArgs& a, uint32_t nblk, u
     uint32_t g0 = chunk * gpw * (uint32_t)TPW;
     if (g0 >= nblk) return;
     if constexpr (M::IN == kInSamples) load_group_rows<TPW, S>(a, g0, min((uint32_t)TPW, nblk - g0), rows);
+    if constexpr (prefetch_zone<S, M>()) load_zone_words<TPW, S, M>(a, g0, min((uint32_t)TPW, nblk - g0), rows);
     if constexpr (PF) {
         const uint32_t gend = min(nblk, g0 + gpw * (uint32_t)TPW);
         for (uint32_t k = 0; g0 < gend; ++k, g0 += (uint32_t)TPW) {
@@ -868,5 +952,14 @@ inline uint32_t groups_per_wg(uint32_t nblk) {
     uint32_t g = (groups + ADCT_TARGET_WGS - 1) / ADCT_TARGET_WGS;
     return g < 1 ? 1 : (g > ADCT_MAX_GPW ? ADCT_MAX_GPW : g);
 }
+
+#ifndef ADCT_ZONE_GPW
+#define ADCT_ZONE_GPW 2
+#endif
+// Groups per workgroup, at least, of the launches that request their zone
+// words a group ahead (prefetch_zone): with one group there is nothing to
+// request ahead.
+constexpr uint32_t kZoneGpw = ADCT_ZONE_GPW;
+static_assert(kZoneGpw >= 1 && kZoneGpw <= ADCT_MAX_GPW, "groups per workgroup");
 
 }  // namespace adct

@@ -70,9 +70,11 @@ constexpr uint32_t log2_pow2(uint32_t n) { return n <= 1 ? 0 : 1 + log2_pow2(n >
 
 // `shared_lines`: the launch writes uint8 rows whose tile-group segments
 // share lines with their neighbours' (kXcdRegions regions, see there).
-GroupGrid group_grid(uint32_t nblk, bool sse, uint32_t image_tiles, bool shared_lines = false) {
+GroupGrid group_grid(uint32_t nblk, bool sse, uint32_t image_tiles, bool shared_lines = false,
+                     uint32_t min_gpw = 1) {
     GroupGrid g;
     g.gpw = groups_per_wg(nblk);
+    if (g.gpw < min_gpw) g.gpw = min_gpw;
     const uint32_t span = g.gpw * (uint32_t)kTPW;
     const uint32_t chunks = (nblk + span - 1) / span;
     const uint32_t n = shared_lines ? kXcdRegions : kSseSpread;
@@ -93,7 +95,8 @@ bool output_shares_lines(const GroupArgs& a) {
 template <typename S, typename M>
 int launch_group(uint32_t nblk, hipStream_t s, const GroupArgs& a) {
     if (nblk == 0) return ADCT_OK;
-    const GroupGrid g = group_grid(nblk, M::SSE && a.sse, a.image_tiles, output_shares_lines<S, M>(a));
+    const GroupGrid g = group_grid(nblk, M::SSE && a.sse, a.image_tiles, output_shares_lines<S, M>(a),
+                                   prefetch_zone<S, M>() ? kZoneGpw : 1u);
     if (g.gpw == 1)
         hipLaunchKernelGGL((k_group<kTPW, S, M, false>), dim3(g.grid), dim3(kTPW * 8), 0, s, a, nblk, g.gpw, g.rows,
                            g.log2);
