@@ -956,6 +956,26 @@ inline uint32_t groups_per_wg(uint32_t nblk) {
 #ifndef ADCT_ZONE_GPW
 #define ADCT_ZONE_GPW 2
 #endif
+#ifndef ADCT_SSE_GPW
+#define ADCT_SSE_GPW 2
+#endif
+// Groups per workgroup, at least, of the plain launches that add to the SSE
+// of images of at most kSseSpreadMin groups.  A workgroup adds its sum to its
+// image's slot with one device-scope atomic when it ends.  The workgroups of
+// such an image run side by side and end together: with one group per
+// workgroup the 64 atomics of each 512 x 512 image cost the headline encoder
+// 7 % (288 against 267 us per call with the atomic left out, 1024 such
+// images), and two groups per workgroup, half the atomics, took it to 270-274
+// us (quantising and zig-zag encoders 7 % faster too).  Larger images are
+// dealt in interleaved streams, which spread their atomics out in time; two
+// groups per workgroup made them slower (4096 images of 1024^2 4.40 against
+// 4.60 ms, 1008^2 4.45 against 4.90 ms, the video frames 223 against 237 us).
+constexpr uint32_t kSseGpw = ADCT_SSE_GPW;
+inline bool sse_gathers(bool sse, uint32_t image_tiles) {
+    return sse && image_tiles / (uint32_t)kTPW <= kSseSpreadMin;
+}
+static_assert(kSseGpw >= 1 && kSseGpw <= ADCT_MAX_GPW, "groups per workgroup");
+
 // Groups per workgroup, at least, of the launches that request their zone
 // words a group ahead (prefetch_zone): with one group there is nothing to
 // request ahead.

@@ -96,7 +96,9 @@ template <typename S, typename M>
 int launch_group(uint32_t nblk, hipStream_t s, const GroupArgs& a) {
     if (nblk == 0) return ADCT_OK;
     const GroupGrid g = group_grid(nblk, M::SSE && a.sse, a.image_tiles, output_shares_lines<S, M>(a),
-                                   prefetch_zone<S, M>() ? kZoneGpw : 1u);
+                                   prefetch_zone<S, M>()                  ? kZoneGpw
+                                   : sse_gathers(M::SSE && a.sse, a.image_tiles) ? kSseGpw
+                                                                                 : 1u);
     if (g.gpw == 1)
         hipLaunchKernelGGL((k_group<kTPW, S, M, false>), dim3(g.grid), dim3(kTPW * 8), 0, s, a, nblk, g.gpw, g.rows,
                            g.log2);
@@ -513,7 +515,8 @@ int adct_encode_quant_planes(const adct_quant_job* jobs, int32_t njobs, int qp, 
         sse_fields(&j.dst, &j.src, j.image_height, j.sse, a);
         const bool shared =
             dt == ADCT_U8 && (((uintptr_t)a.dst.data | (uint64_t)a.dst.pitch | (uint64_t)a.bw * 16u) & 127u) != 0;
-        const GroupGrid g = group_grid((uint32_t)nblk, want_sse, a.image_tiles, shared);
+        const GroupGrid g = group_grid((uint32_t)nblk, want_sse, a.image_tiles, shared,
+                                       sse_gathers(want_sse, a.image_tiles) ? kSseGpw : 1u);
         pl.nblk = (uint32_t)nblk;
         pl.gpw = g.gpw;
         pl.spread_rows = g.rows;
