@@ -1,6 +1,8 @@
 // The tile-group processor: every device entry point is one configuration
-// of `process_group`, either launched one group per workgroup (plain calls)
-// or called in a loop by a persistent workgroup (batches, serving).
+// of `process_group`, either run over a short chunk of groups per workgroup
+// (plain calls: one group, or two where that pays, see kSseGpw and
+// kZoneGpw) or called in a loop by a persistent workgroup (batches,
+// serving).
 //
 // A group is TPW tiles of one plane, consecutive in raster order.  It is
 // processed by 8 * TPW threads; each thread owns two sample rows (i, i+8) of

@@ -61,8 +61,8 @@ int check_recon(const adct_plane* dst, const adct_plane* ref, int32_t image_heig
 }
 
 // Grid of a plain launch over nblk tiles: groups_per_wg groups per
-// workgroup; launches that add to the SSE of large images interleave their
-// chunks.
+// workgroup, at least min_gpw; launches that add to the SSE of large images
+// interleave their chunks.
 struct GroupGrid {
     uint32_t gpw, rows, log2, grid;
 };
