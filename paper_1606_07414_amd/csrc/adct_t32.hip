@@ -152,9 +152,10 @@ __device__ __forceinline__ void column_factors32(const Scale5& t, int v, float (
 // Workgroup b of a launch over the plane of `a` (256 threads).  RB bounds
 // the zonal size at compile time (r <= RB): the coefficients with u or v >=
 // RB are then known zeros, and the inverse passes, unrolled, drop every
-// addition of such a zero (a zonal launch takes the least of 8, 16 and 32
-// that holds r).  SAT: the quantiser saturates its levels to int16 (the
-// host leaves it out where they provably fit).
+// addition of such a zero (a zonal launch without a coefficient output
+// takes the least of 8, 16 and 32 that holds r).  SAT: the quantiser
+// saturates its levels to int16 (the host leaves it out where they provably
+// fit).
 template <typename S, int OP, bool STORE, bool SSE, int RB = 32, bool SAT = true>
 __device__ __forceinline__ void t32_group(const Args32& a, uint32_t b) {
     __shared__ __align__(16) int32_t lds[kTiles32 * kTile32];
@@ -386,7 +387,11 @@ void launch32_rb(const Args32& a, hipStream_t s) {
 
 template <typename S, int OP, bool STORE>
 void launch32(const Args32& a, hipStream_t s) {
-    if constexpr (OP == kZonal32) {
+    // The bound pays where the launch is bound by issue, without the
+    // coefficient output (r = 8: 196 against 160 us on 1024 images of 512^2).
+    // With it the launch streams 6 KB per block, and the bounded kernels were
+    // the slower ones: 300-302 against 280-285 us at r = 4 and 8.
+    if constexpr (OP == kZonal32 && !STORE) {
         if (a.r <= 8) return launch32_rb<S, OP, STORE, 8>(a, s);
         if (a.r <= 16) return launch32_rb<S, OP, STORE, 16>(a, s);
     }
