@@ -63,6 +63,9 @@ __device__ __forceinline__ bool claim_item(const BatchArgs& b, uint32_t home, ui
 template <int TPW, typename S, typename M>
 __global__ __launch_bounds__(TPW * 8) void k_batch(BatchArgs b, const GroupArgs* __restrict__ jobs,
                                                    const ItemDev* __restrict__ items) {
+    // the loop below loads each next group's sample rows itself; the zone
+    // words of a zonal reconstruction are set up by group_chunk only
+    static_assert(M::IN == kInSamples, "the batch codes samples");
     __shared__ uint32_t lds[lds_words(TPW)];
     __shared__ long long red[TPW * 8 / 64];
     __shared__ uint32_t sh_claim;
